@@ -1,0 +1,308 @@
+"""Pins of the FP64 oracle against facts fixed outside it.
+
+Each test names the passage of the paper (or the mathematical fact) that
+fixes the quantity.  None of them re-types the oracle's own formulas: they
+check closed forms, identities and brute force.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from paper_2507_10804_amd import synth
+from tests._cases import dense_case, rel, tiny
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    oracle.build(force=False)
+
+
+# ---------------------------------------------------------------- Laplacian
+
+@pytest.mark.parametrize("p", range(0, 10))
+def test_laplacian_exact_on_polynomials(p):
+    """An 8th-order centred second difference is exact on polynomials of
+    degree <= 9, so L x^p = p(p-1) x^(p-2) away from the zero ghosts."""
+    n, dx = 40, 0.05
+    z = (np.arange(n) - n / 2 + 0.3) * dx
+    x = (np.arange(n) - n / 2 - 0.2) * dx
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    for u, exact in [
+        (X ** p, p * (p - 1) * X ** max(p - 2, 0) if p >= 2 else 0 * X),
+        (Z ** p, p * (p - 1) * Z ** max(p - 2, 0) if p >= 2 else 0 * Z),
+    ]:
+        lu = oracle.laplacian(u, dx)
+        inner = (slice(4, -4), slice(4, -4))
+        scale = max(np.abs(u[inner]).max() / dx ** 2, 1.0)
+        assert np.abs(lu[inner] - exact[inner]).max() <= 1e-12 * scale
+
+
+def test_laplacian_mixed_and_zero_ghosts():
+    """L(x^3 z^4) = 6 x z^4 + 12 x^3 z^2 inside; outside values are zero, so
+    a single unit spike reproduces the stencil weights of a second derivative
+    of a delta (centre weight 2 * -205/72 / dx^2)."""
+    n, dx = 30, 0.1
+    z = (np.arange(n) - 15.0) * dx
+    x = (np.arange(n) - 14.5) * dx
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    lu = oracle.laplacian(X ** 3 * Z ** 4, dx)
+    ex = 6 * X * Z ** 4 + 12 * X ** 3 * Z ** 2
+    assert np.abs(lu[4:-4, 4:-4] - ex[4:-4, 4:-4]).max() < 1e-10
+    spike = np.zeros((9, 9))
+    spike[4, 4] = 1.0
+    ls = oracle.laplacian(spike, 1.0)
+    assert ls[4, 4] == pytest.approx(-2 * 205.0 / 72.0, rel=1e-15)
+    # symmetric operator: <L a, b> = <a, L b> with zero ghosts
+    rng = np.random.default_rng(1)
+    a, b = rng.standard_normal((2, 13, 17))
+    assert np.vdot(oracle.laplacian(a, 1.3), b) == pytest.approx(
+        np.vdot(a, oracle.laplacian(b, 1.3)), rel=1e-13)
+
+
+# ------------------------------------------------------------ Green's function
+
+def _green_trace(t, r, c, f0):
+    """2-D free-space response of (1/c^2) u_tt - lap u = s(t) delta(x):
+    u(r, t) = 1/(2 pi) int_0^acosh(ct/r) s(t - (r/c) cosh th) dth."""
+    t0 = 1.5 / f0
+    out = np.zeros_like(t)
+    for i, ti in enumerate(t):
+        if c * ti <= r:
+            continue
+        top = math.acosh(c * ti / r)
+
+        def s(th):
+            a = (math.pi * f0 * (ti - (r / c) * math.cosh(th) - t0)) ** 2
+            return (1 - 2 * a) * math.exp(-a)
+
+        out[i] = integrate.quad(s, 0.0, top, limit=400, epsabs=1e-13)[0] / (2 * math.pi)
+    return out
+
+
+def _homog_trace(dx, c=2000.0, half=900.0, offset=500.0, T=0.6, f0=10.0):
+    n = int(round(2 * half / dx)) + 1
+    mid = n // 2
+    nt = int(round(T / (0.4 * dx / c))) + 1
+    g = synth.make_geometry(n, n, dx=dx, nt=nt, ns=1, rec_ix=[mid + int(round(offset / dx))],
+                            f0=f0, v_nominal=c, src_zx=[[mid, mid]], rec_iz=mid)
+    m = np.full((n, n), c)
+    d = oracle.forward(g, m)[0, :, 0]
+    t = np.arange(nt) * g.dt
+    return t, d, _green_trace(t, offset, c, f0)
+
+
+def test_green_function_convergence():
+    """Forward solve against the analytic 2-D Green's function of eq. (1)
+    (Section 2; homogeneous m, point source s(t) delta(x - x_s)).  The
+    leapfrog scheme at a fixed Courant number converges at second order."""
+    errs = []
+    for dx in (20.0, 10.0, 5.0):
+        t, d, ex = _homog_trace(dx)
+        errs.append(rel(d, ex))
+    o1 = math.log2(errs[0] / errs[1])
+    o2 = math.log2(errs[1] / errs[2])
+    assert errs[2] < 0.01, errs
+    assert 1.6 < o1 < 2.6 and 1.6 < o2 < 2.6, (errs, o1, o2)
+
+
+# ---------------------------------------------------------------- reciprocity
+
+def test_reciprocity_heterogeneous_with_sponge():
+    """Swapping source and receiver leaves the trace unchanged: the scheme is
+    symmetric in space (diagonal coefficients, symmetric L), with the sponge
+    on and a heterogeneous model."""
+    g, m = tiny(nt=300)
+    A, B = (3, 7), (25, 40)
+    g2 = synth.make_geometry(g.nx, g.nz, nt=g.nt, ns=2, rec_ix=[0], f0=g.f0,
+                             v_nominal=2300.0, nb=g.nb, src_zx=[A, B])
+    g2.rec_zx = np.array([B, A], dtype=np.int32)
+    d = oracle.forward(g2, m)
+    ab, ba = d[0, :, 0], d[1, :, 1]
+    assert np.abs(ab).max() > 1e-6
+    assert rel(ab, ba) < 1e-12
+
+
+# ------------------------------------------------------------------ stability
+
+def test_stability_limit():
+    """Leapfrog with the 8th-order Laplacian is stable up to Courant number
+    2/sqrt(2*6.5012) = 0.5546: 0.55 stays bounded, 0.56 blows up."""
+    n = 40
+    out = {}
+    for cfl in (0.55, 0.56):
+        g = synth.make_geometry(n, n, nt=700, ns=1, rec_ix=[10], f0=15.0, v_nominal=2000.0,
+                                cfl=cfl, nb=10)
+        d = oracle.forward(g, np.full((n, n), 2000.0))
+        out[cfl] = np.abs(d).max()
+    assert np.isfinite(out[0.55]) and out[0.55] < 1.0
+    assert not np.isfinite(out[0.56]) or out[0.56] > 1e8
+
+
+# ----------------------------------------------------- sponge (sanity only)
+
+def test_sponge_absorbs():
+    """The absorbing layer is a chosen convention (parity unpinned by the
+    paper).  Sanity: once the direct wave has left, what comes back from the
+    pad is a small fraction of it, and the field decays instead of growing."""
+    n = 80
+    g = synth.make_geometry(n, n, nt=1400, ns=1, rec_ix=[40], f0=15.0, v_nominal=2000.0,
+                            nb=20, src_zx=[[40, 40]], rec_iz=40)
+    h = oracle.wavefield(g, np.full((n, n), 2000.0))
+    inner = h[:, 20:-20, 20:-20]
+    peak = np.abs(inner[:300]).max()
+    late = np.abs(inner[900:]).max()
+    assert late < 0.02 * peak, (late, peak)
+    energy = (h ** 2).sum(axis=(1, 2))
+    assert energy[-1] < 1e-3 * energy.max()
+
+
+# ------------------------------------------------------- derivative checks
+
+def _setup(nt=250):
+    g, m = tiny(nt=nt)
+    v = synth.smooth_random(m.shape, seed=1, sigma=3.0)
+    return g, m, v
+
+
+def test_born_matches_finite_difference():
+    """F = grad f (Section 2.1): the Born data equals the central difference
+    of the forward map, with the O(h^2) error falling ~4x per halving of h."""
+    g, m, v = _setup()
+    jv = oracle.born(g, m, v)
+    errs = []
+    for h0 in (2e-3, 1e-3):
+        h = h0 * np.abs(m).max() / np.abs(v).max()
+        fd = (oracle.forward(g, m + h * v) - oracle.forward(g, m - h * v)) / (2 * h)
+        errs.append(rel(fd, jv))
+    assert errs[1] < 1e-5, errs
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_dot_product_identity():
+    """<J v, r> = <v, J^T r> (F* is the adjoint of F, Section 2.1)."""
+    g, m, v = _setup()
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=2)
+    lhs = np.vdot(oracle.born(g, m, v), r)
+    rhs = np.vdot(v, oracle.adjoint(g, m, r))
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_gradient_matches_finite_difference():
+    """eq. grad (Section 2.1, misfit half): <grad Phi, v> equals the central
+    difference of Phi along v."""
+    g, m, v = _setup()
+    m_true = m.copy()
+    m0 = synth.smooth(m_true, 3.0)
+    dobs = oracle.forward(g, m_true)
+    phi, grad = oracle.misfit_grad(g, m0, dobs)
+    assert phi > 0
+    # Phi by definition from the forward map
+    assert phi == pytest.approx(0.5 * np.sum((oracle.forward(g, m0) - dobs) ** 2), rel=1e-13)
+    exact = np.vdot(grad, v)
+    fds = []
+    for h0 in (1e-3, 5e-4):
+        h = h0 * np.abs(m0).max() / np.abs(v).max()
+        fp, _ = oracle.misfit_grad(g, m0 + h * v, dobs)
+        fm, _ = oracle.misfit_grad(g, m0 - h * v, dobs)
+        fds.append((fp - fm) / (2 * h))
+    e = [abs(f - exact) / abs(exact) for f in fds]
+    assert e[1] < 1e-4 and 3.5 < e[0] / e[1] < 4.5, e
+    # Richardson extrapolation removes the O(h^2) term
+    assert (4 * fds[1] - fds[0]) / 3 == pytest.approx(exact, rel=1e-7)
+
+
+def test_gradient_noise_weight_and_adjoint_form():
+    """grad = inv_noise_var J^T (f(m) - d) (eq. grad with Gamma_noise = sigma^2 I)."""
+    g, m, v = _setup(nt=150)
+    dobs = oracle.forward(g, synth.smooth(m, 2.0))
+    g.inv_noise_var = 4.0
+    phi, grad = oracle.misfit_grad(g, m, dobs)
+    res = oracle.forward(g, m) - dobs
+    assert phi == pytest.approx(2.0 * np.sum(res ** 2), rel=1e-13)
+    assert rel(grad, 4.0 * oracle.adjoint(g, m, res)) < 1e-13
+
+
+def test_hessian_symmetric_psd_and_gauss_newton():
+    """H_d (Section 3) is applied as the Gauss-Newton normal operator
+    J^T Gamma^-1 J: symmetric, <v, Hv> = inv_noise_var |J v|^2 >= 0."""
+    g, m, v = _setup(nt=200)
+    u = synth.smooth_random(m.shape, seed=7, sigma=3.0)
+    hv = oracle.gn_hvp(g, m, v)
+    hu = oracle.gn_hvp(g, m, u)
+    assert np.vdot(u, hv) == pytest.approx(np.vdot(hu, v), rel=1e-12)
+    jv = oracle.born(g, m, v)
+    assert np.vdot(v, hv) == pytest.approx(np.sum(jv ** 2), rel=1e-12)
+    assert np.vdot(v, hv) > 0
+    # linearity
+    assert rel(oracle.gn_hvp(g, m, 2.0 * v - 3.0 * u), 2.0 * hv - 3.0 * hu) < 1e-12
+
+
+def test_hessian_zero_residual_identity():
+    """At a zero-residual model the full misfit Hessian equals the Gauss-Newton
+    one, so the central difference of the gradient reproduces H v (O(h^2))."""
+    g, m, v = _setup(nt=200)
+    dobs = oracle.forward(g, m)
+    hv = oracle.gn_hvp(g, m, v)
+    errs = []
+    for h0 in (2e-3, 1e-3):
+        h = h0 * np.abs(m).max() / np.abs(v).max()
+        _, gp = oracle.misfit_grad(g, m + h * v, dobs)
+        _, gm = oracle.misfit_grad(g, m - h * v, dobs)
+        errs.append(rel((gp - gm) / (2 * h), hv))
+    assert errs[1] < 1e-4, errs
+    assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+def test_shot_sum_and_batch():
+    """H_d sums per-source contributions ("two wave equations per source",
+    Section 3): H v over all shots equals the sum of single-shot products,
+    and a batch of vectors equals one call per vector."""
+    g, m, v = _setup(nt=150)
+    u = synth.smooth_random(m.shape, seed=9, sigma=3.0)
+    full = oracle.gn_hvp(g, m, v)
+    parts = sum(oracle.gn_hvp(g.with_shots([s]), m, v) for s in range(g.ns))
+    assert rel(parts, full) < 1e-13
+    batch = oracle.gn_hvp(g, m, np.stack([v, u]))
+    assert rel(batch[0], full) == 0.0
+    assert rel(batch[1], oracle.gn_hvp(g, m, u)) == 0.0
+
+
+# ---------------------------------------------------- dense brute force
+
+def test_dense_jacobian_tiny_grid():
+    """Brute force on a 16x16 grid: every Born column J e_i equals the
+    central difference of the forward map; the adjoint equals the dense
+    transpose; H v equals the dense J^T J v."""
+    g, m = dense_case()
+    nz, nx = m.shape
+    N = nz * nx
+    cols = []
+    fdcols = []
+    rng = np.random.default_rng(5)
+    pick = rng.choice(N, size=24, replace=False)
+    for i in range(N):
+        e = np.zeros(N)
+        e[i] = 1.0
+        cols.append(oracle.born(g, m, e.reshape(nz, nx)).ravel())
+    J = np.stack(cols, axis=1)
+    for i in pick:
+        e = np.zeros(N)
+        e[i] = 1.0
+        h = 0.5
+        fd = (oracle.forward(g, m + h * e.reshape(nz, nx)) -
+              oracle.forward(g, m - h * e.reshape(nz, nx))).ravel() / (2 * h)
+        fdcols.append(rel(fd, J[:, i]))
+    assert max(fdcols) < 1e-6, max(fdcols)
+    for seed in (11, 12):
+        r = np.random.default_rng(seed).standard_normal(J.shape[0])
+        jt = oracle.adjoint(g, m, r.reshape(g.ns, g.nt, g.nr)).ravel()
+        assert rel(jt, J.T @ r) < 1e-12
+    H = J.T @ J
+    v = synth.smooth_random((nz, nx), seed=13, sigma=2.0)
+    assert rel(oracle.gn_hvp(g, m, v).ravel(), H @ v.ravel()) < 1e-12
+    # symmetric and positive semidefinite as a matrix
+    w = np.linalg.eigvalsh(0.5 * (H + H.T))
+    assert w.min() > -1e-10 * w.max()
