@@ -1,0 +1,168 @@
+/*
+ * fwi.h -- C ABI of the MI355X (gfx950) library for matrix-free Gauss-Newton
+ * Hessian-vector products of 2-D constant-density acoustic full-waveform
+ * inversion.
+ *
+ * The operations follow the paper's statement of the problem:
+ *   - eq. (1), Section 2: (1/m^2) u_tt - lap u = s(t) delta(x - x_s), with m
+ *     the wave speed; the forward map f records u at the receivers;
+ *   - Section 2: data model d = f(m) + eta, eta ~ N(0, sigma^2 I), and the
+ *     data misfit 1/2 |f(m) - d|^2 weighted by 1/sigma^2;
+ *   - eq. "grad", Section 2.1: the misfit gradient F* Gamma^-1 (f(m) - d),
+ *     F = grad f the Born operator and F* its adjoint (migration);
+ *   - Section 3: the misfit Hessian H_d applied matrix-free to vectors, one
+ *     Born and one adjoint solve per source (plus the forward solve at a new
+ *     model), as the Gauss-Newton normal operator F* Gamma^-1 F.
+ *
+ * Discretisation (the paper leaves it open): padded grid of (nz+2nb) rows by
+ * (nx+2nb) columns with zero values outside it; 8th-order centred Laplacian;
+ * second-order leapfrog in time; quadratic absorbing sponge in the nb pad
+ * cells, kappa = kappa_max((cells into the pad in x / nb)^2 + (... in z / nb)^2);
+ * velocity in the pad replicated from the nearest model cell (its derivative
+ * folds back onto the edge cells); point source s(n dt)/dx^2 at the shot node;
+ * receivers sample nodes; u^{-1} = u^0 = 0.  All results are exact
+ * derivatives of this discrete forward map (discretise-then-differentiate).
+ *
+ * Memory and ownership.  The library never allocates device memory.  The
+ * caller owns (1) the plan's device block, bound once with fwi_plan_bind(),
+ * and (2) a workspace per call, sized by fwi_workspace_size(); all array
+ * arguments of the compute calls are DEVICE pointers to contiguous row-major
+ * FP32 arrays, except `phi`, a device double.  A plan copies the host
+ * geometry it is given; it is not thread-safe: one plan per stream.
+ *
+ * Layouts (x is the fastest axis):
+ *   model-space arrays m, v, g, hv:   [B][nz][nx]
+ *   data-space arrays d, dd, r, dobs: [B][ns][nt][nr] (receiver fastest)
+ *
+ * Asynchrony.  Every compute call validates its arguments synchronously,
+ * enqueues kernels on `stream` (a hipStream_t; NULL = the default stream) and
+ * returns; outputs are valid once the stream has completed.  The enqueued
+ * work contains kernel launches only (no memset, no host copies), so a call
+ * can be captured into a hipGraph and replayed, provided the plan's device
+ * block and the workspace stay where they are.
+ *
+ * Errors.  Return codes are FWI_OK or a negative FWI_E* value; nothing aborts
+ * or throws across the ABI.  Argument and size errors are reported
+ * synchronously with a message retrievable by fwi_last_error() (thread
+ * local).  Data-dependent conditions found on the device (m <= 0 or not
+ * finite, Courant number above the stability limit, non-finite output) are
+ * OR-ed into a status word read and cleared by fwi_status().
+ */
+#ifndef FWI_MI355X_H
+#define FWI_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FWI_ABI_VERSION 1
+
+enum {
+  FWI_OK = 0,
+  FWI_EINVAL = -1,     /* bad argument, shape or position */
+  FWI_EUNSTABLE = -2,  /* reserved: reported through the status word */
+  FWI_ENOMEM = -3,     /* workspace or device block too small */
+  FWI_EHIP = -4,       /* a HIP runtime call failed */
+  FWI_ENUMERIC = -5,   /* reserved: reported through the status word */
+  FWI_EUNBOUND = -6    /* plan has no device block yet (fwi_plan_bind) */
+};
+
+/* Bits of the device status word (fwi_status). */
+enum {
+  FWI_STATUS_BAD_MODEL = 1,   /* some m <= 0 or not finite */
+  FWI_STATUS_CFL = 2,         /* max(m) dt / dx above 0.5546 */
+  FWI_STATUS_NONFINITE = 4    /* an output held inf or nan */
+};
+
+/* Operations, for fwi_workspace_size. */
+enum {
+  FWI_OP_FORWARD = 0,
+  FWI_OP_BORN = 1,
+  FWI_OP_ADJOINT = 2,
+  FWI_OP_MISFIT_GRAD = 3,
+  FWI_OP_GN_HVP = 4
+};
+
+typedef struct fwi_plan fwi_plan;
+
+/* Host-side description of one problem.  All pointers are HOST pointers and
+ * are copied by fwi_plan_create. */
+typedef struct {
+  int32_t nx, nz;          /* model grid: nz rows (depth) x nx columns, nx fastest */
+  int32_t nb;              /* absorbing cells padded on each side (>= 0) */
+  int32_t nt;              /* time samples n = 0..nt-1 (>= 2) */
+  float dx;                /* grid spacing in metres (dz = dx) */
+  float dt;                /* time step in seconds, fixed by the plan */
+  float kappa_max;         /* peak sponge damping (>= 0, < 1/2) */
+  int32_t ns;              /* shots */
+  const int32_t *src_zx;   /* ns x (iz, ix) model cells */
+  int32_t nr;              /* receivers, shared by all shots */
+  const int32_t *rec_zx;   /* nr x (iz, ix) model cells */
+  const float *wavelet;    /* nt samples s(n dt) */
+  int32_t ckpt_every;      /* K: forward checkpoint interval in steps (>= 1) */
+  double inv_noise_var;    /* 1/sigma^2 weighting of the misfit */
+} fwi_geometry;
+
+int fwi_abi_version(void);
+
+/* Validate `g` and build the host plan (receiver/tile tables).  No HIP
+ * call.  Returns FWI_EINVAL for a bad size, spacing, position or K. */
+int fwi_plan_create(const fwi_geometry *g, fwi_plan **out);
+void fwi_plan_destroy(fwi_plan *p);
+
+/* Size in bytes of the plan's device block (tables, positions, status). */
+int fwi_plan_device_bytes(const fwi_plan *p, size_t *bytes);
+
+/* Upload the plan's tables into caller-owned device memory `dev` (at least
+ * fwi_plan_device_bytes, 256-byte aligned) and keep the pointer.  Blocks
+ * until the copy is done.  Must precede every compute call. */
+int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream);
+
+/* Workspace bytes for operation `op` with `batch` vectors (1 for
+ * FORWARD / MISFIT_GRAD).  Workspaces must be 256-byte aligned. */
+int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes);
+
+/* Padded-grid geometry the kernels use (for tools and tests):
+ * dims[0..5] = NZp, NXp, row pitch (floats), tile rows, tile columns, K. */
+int fwi_plan_dims(const fwi_plan *p, int32_t dims[6]);
+
+/* Forward map (Section 2): d[ns][nt][nr] = R u_s^n for every shot. */
+int fwi_forward(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_bytes,
+                void *stream);
+
+/* Born modelling (Section 2.1, F = grad f): dd[B][ns][nt][nr] = J v_b for the
+ * B model perturbations v[B][nz][nx]. */
+int fwi_born(fwi_plan *p, const float *m, const float *v, int B, float *dd, void *ws,
+             size_t ws_bytes, void *stream);
+
+/* Migration (Section 2.1, F*): g[B][nz][nx] = sum_s J_s^T r_{b,s} for the B
+ * data vectors r[B][ns][nt][nr] (no noise weighting). */
+int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *g, void *ws,
+                size_t ws_bytes, void *stream);
+
+/* Data misfit and its gradient (Section 2.1, eq. grad, misfit half):
+ * *phi (device double) = 1/2 inv_noise_var sum |d(m) - dobs|^2,
+ * g[nz][nx] = inv_noise_var sum_s J_s^T (d_s(m) - dobs_s). */
+int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi, float *g,
+                    void *ws, size_t ws_bytes, void *stream);
+
+/* Gauss-Newton misfit Hessian times B vectors (Section 3):
+ * hv[B][nz][nx] = inv_noise_var sum_s J_s^T J_s v_b.  The forward solve and
+ * its recomputation are shared by the whole batch. */
+int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, void *ws,
+               size_t ws_bytes, void *stream);
+
+/* Synchronise `stream`, return the device status word in *status and clear
+ * it. */
+int fwi_status(fwi_plan *p, void *stream, uint32_t *status);
+
+const char *fwi_strerror(int code);
+const char *fwi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FWI_MI355X_H */

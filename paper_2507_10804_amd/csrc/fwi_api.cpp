@@ -1,0 +1,522 @@
+// Host side of the C ABI declared in include/fwi.h: plan construction
+// (validation, receiver/tile tables), workspace planning and the time loops
+// of each operation.  The library never allocates device memory: tables live
+// in a caller-owned device block, scratch in a caller-owned workspace.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/fwi.h"
+#include "fwi_internal.h"
+
+namespace fwi {
+hipError_t launch_step(const Geo &g, const DevTables &t, const StepArgs &a, bool born,
+                       hipStream_t st);
+hipError_t launch_adjoint(const Geo &g, const DevTables &t, const AdjArgs &a, hipStream_t st);
+hipError_t launch_setup(const Geo &g, const float *m, const float *v, int B, float *c,
+                        float *s2m, float *dc, unsigned int *status, hipStream_t st);
+hipError_t launch_fill(float *p, long long n, hipStream_t st);
+hipError_t launch_fill64(double *p, long long n, hipStream_t st);
+hipError_t launch_zero_t0(float *d, int count, int nt, int nr, hipStream_t st);
+hipError_t launch_residual(float *d, const float *dobs, long long n, double *part, int nparts,
+                           double scale, double *phi, hipStream_t st);
+hipError_t launch_fold(const Geo &g, const double *img, int G, int B, double scale, float *out,
+                       hipStream_t st);
+hipError_t launch_check_finite(const float *p, long long n, unsigned int *status,
+                               hipStream_t st);
+}  // namespace fwi
+
+using namespace fwi;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+  g_last_error = msg;
+  return code;
+}
+
+constexpr size_t ALIGN = 256;
+constexpr int NPARTS = 1024;  // FP64 partial sums of the misfit
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+}  // namespace
+
+struct fwi_plan {
+  Geo geo{};
+  int K = 1, nseg = 1;
+  float dx = 0, dt = 0;
+  double inv_noise_var = 1.0;
+  std::vector<float> wavelet;
+  // device block image, in int32 words, and offsets into it
+  std::vector<int> blk;
+  size_t off_status = 0, off_src = 0, off_trp = 0, off_rloc = 0, off_rid = 0, off_tnp = 0,
+         off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0;
+  void *dev = nullptr;
+  DevTables tabs{};
+  int adj_group_override = 0;
+};
+
+namespace {
+
+// Byte layout of one operation's workspace.
+struct Layout {
+  size_t c = 0, s2m = 0, dc = 0, u = 0, du = 0, dd = 0, dres = 0, part = 0, ckpt = 0,
+         wseg = 0, mu = 0, img = 0, total = 0;
+  int G = 1, group = 1;
+};
+
+int adjoint_group(const fwi_plan *p, int B) {
+  if (p->adj_group_override > 0) return std::min(p->adj_group_override, p->geo.ns);
+  // Enough workgroups to fill 256 CUs several times over, and as many shots
+  // per workgroup as that allows (fewer partial-image updates).
+  const long long base = (long long)p->geo.ntiles * B;
+  int group = 1;
+  while (group < 16 && group * 2 <= p->geo.ns &&
+         base * ((p->geo.ns + group * 2 - 1) / (group * 2)) >= 4096)
+    group *= 2;
+  return group;
+}
+
+Layout layout(const fwi_plan *p, int op, int B) {
+  const Geo &g = p->geo;
+  const size_t F = (size_t)g.fs * sizeof(float);
+  const size_t ndata = (size_t)g.ns * g.nt * g.nr * sizeof(float);
+  const bool needs_dc = op == FWI_OP_BORN || op == FWI_OP_GN_HVP;
+  const bool needs_adj = op == FWI_OP_ADJOINT || op == FWI_OP_MISFIT_GRAD || op == FWI_OP_GN_HVP;
+  const int Badj = op == FWI_OP_MISFIT_GRAD ? 1 : B;
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = o;
+    o = align_up(o + bytes);
+    return at;
+  };
+  L.c = take(F);
+  L.s2m = take(F);
+  if (needs_dc) L.dc = take(F * B);
+  L.u = take(F * 2 * g.ns);
+  if (needs_dc) L.du = take(F * 2 * g.ns * B);
+  if (op == FWI_OP_GN_HVP) L.dd = take(ndata * B);
+  if (op == FWI_OP_MISFIT_GRAD) {
+    L.dres = take(ndata);
+    L.part = take(NPARTS * sizeof(double));
+  }
+  if (needs_adj) {
+    L.group = adjoint_group(p, Badj);
+    L.G = (g.ns + L.group - 1) / L.group;
+    L.ckpt = take(F * 2 * g.ns * p->nseg);
+    L.wseg = take(F * g.ns * p->K);
+    // the Born fields are dead once the forward sweep is over: the adjoint
+    // fields of a Hessian product reuse their memory
+    L.mu = op == FWI_OP_GN_HVP ? L.du : take(F * 2 * g.ns * Badj);
+    L.img = take((size_t)g.fs * sizeof(double) * L.G * Badj);
+  }
+  L.total = o;
+  return L;
+}
+
+template <class T>
+T *at(void *ws, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(FWI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
+  } while (0)
+
+int check_call(const fwi_plan *p, int op, int B, const void *ws, size_t ws_bytes) {
+  if (!p) return fail(FWI_EINVAL, "plan is null");
+  if (!p->dev) return fail(FWI_EUNBOUND, "plan has no device block: call fwi_plan_bind first");
+  if (B < 1 || B > 4096) return fail(FWI_EINVAL, "batch must be in [1, 4096]");
+  const size_t need = layout(p, op, B).total;
+  if (!ws || ws_bytes < need)
+    return fail(FWI_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  if (reinterpret_cast<uintptr_t>(ws) % ALIGN)
+    return fail(FWI_EINVAL, "workspace must be 256-byte aligned");
+  return FWI_OK;
+}
+
+float src_amp(const fwi_plan *p, int n) { return p->wavelet[n] / (p->dx * p->dx); }
+
+// Forward sweep n = 0..nt-2 on the fields at ws+L.u (and Born fields).
+int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, float *d_out,
+                  float *dd_out, bool store_ckpt, hipStream_t st) {
+  const Geo &g = p->geo;
+  StepArgs a{};
+  a.c = at<float>(ws, L.c);
+  a.dc = born ? at<float>(ws, L.dc) : nullptr;
+  a.u = at<float>(ws, L.u);
+  a.du = born ? at<float>(ws, L.du) : nullptr;
+  a.B = born ? B : 0;
+  a.d_out = d_out;
+  a.dd_out = dd_out;
+  float *ckpt = store_ckpt ? at<float>(ws, L.ckpt) : nullptr;
+  for (int n = 0; n + 1 < g.nt; ++n) {
+    a.n = n;
+    a.src_amp = src_amp(p, n);
+    a.ck = nullptr;
+    if (ckpt && (n + 1) % p->K == 0) {
+      const int j = (n + 1) / p->K;
+      if (j < p->nseg) a.ck = ckpt + (size_t)j * 2 * g.ns * g.fs;
+    }
+    HIP_TRY(launch_step(g, p->tabs, a, born, st));
+  }
+  return FWI_OK;
+}
+
+// Reverse sweep: segment-wise recompute of w^n from the checkpoints, then the
+// adjoint steps k = nt-1..0 with injection of r[B][ns][nt][nr].  Leaves the
+// partial images in ws+L.img.
+int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
+                  hipStream_t st) {
+  const Geo &g = p->geo;
+  HIP_TRY(launch_fill(at<float>(ws, L.mu), (long long)g.fs * 2 * g.ns * B, st));
+  HIP_TRY(launch_fill64(at<double>(ws, L.img), (long long)g.fs * L.G * B, st));
+  StepArgs f{};
+  f.c = at<float>(ws, L.c);
+  AdjArgs a{};
+  a.c = at<float>(ws, L.c);
+  a.s2m = at<float>(ws, L.s2m);
+  a.mu = at<float>(ws, L.mu);
+  a.r = r;
+  a.img = at<double>(ws, L.img);
+  a.B = B;
+  a.group = L.group;
+  a.ngroups = L.G;
+  float *ckpt = at<float>(ws, L.ckpt);
+  float *wseg = at<float>(ws, L.wseg);
+  for (int j = p->nseg - 1; j >= 0; --j) {
+    const int n0 = j * p->K;
+    const int n1 = std::min((j + 1) * p->K, g.nt - 1);
+    f.u = ckpt + (size_t)j * 2 * g.ns * g.fs;  // recomputed in place: used once
+    for (int n = n0; n < n1; ++n) {
+      f.n = n;
+      f.src_amp = src_amp(p, n);
+      f.w_out = wseg + (size_t)(n - n0) * g.ns * g.fs;
+      HIP_TRY(launch_step(g, p->tabs, f, false, st));
+    }
+    const int ktop = (j == p->nseg - 1) ? g.nt - 1 : n1 - 1;
+    for (int k = ktop; k >= n0; --k) {
+      a.k = k;
+      a.w = (k <= g.nt - 2) ? wseg + (size_t)(k - n0) * g.ns * g.fs : nullptr;
+      HIP_TRY(launch_adjoint(g, p->tabs, a, st));
+    }
+  }
+  return FWI_OK;
+}
+
+int prologue(fwi_plan *p, const Layout &L, void *ws, const float *m, const float *v, int B,
+             bool born, bool adj, hipStream_t st) {
+  const Geo &g = p->geo;
+  HIP_TRY(launch_setup(g, m, v, B, at<float>(ws, L.c), at<float>(ws, L.s2m),
+                       born ? at<float>(ws, L.dc) : nullptr, p->tabs.status, st));
+  HIP_TRY(launch_fill(at<float>(ws, L.u), (long long)g.fs * 2 * g.ns, st));
+  if (born) HIP_TRY(launch_fill(at<float>(ws, L.du), (long long)g.fs * 2 * g.ns * B, st));
+  if (adj) HIP_TRY(launch_fill(at<float>(ws, L.ckpt), (long long)g.fs * 2 * g.ns, st));
+  return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwi_abi_version(void) { return FWI_ABI_VERSION; }
+
+const char *fwi_strerror(int code) {
+  switch (code) {
+    case FWI_OK: return "ok";
+    case FWI_EINVAL: return "invalid argument";
+    case FWI_EUNSTABLE: return "unstable time step";
+    case FWI_ENOMEM: return "workspace or device block too small";
+    case FWI_EHIP: return "HIP runtime error";
+    case FWI_ENUMERIC: return "non-finite result";
+    case FWI_EUNBOUND: return "plan not bound to a device block";
+    default: return "unknown error";
+  }
+}
+
+const char *fwi_last_error(void) { return g_last_error.c_str(); }
+
+int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
+  if (!gi || !out) return fail(FWI_EINVAL, "null argument");
+  *out = nullptr;
+  const fwi_geometry &G = *gi;
+  if (G.nx < 1 || G.nz < 1) return fail(FWI_EINVAL, "nx and nz must be >= 1");
+  if (G.nb < 0 || G.nb > 1000) return fail(FWI_EINVAL, "nb must be in [0, 1000]");
+  if (G.nt < 2) return fail(FWI_EINVAL, "nt must be >= 2");
+  if (G.ns < 1 || G.nr < 1) return fail(FWI_EINVAL, "need at least one shot and one receiver");
+  if (!(G.dx > 0.f) || !(G.dt > 0.f) || !std::isfinite(G.dx) || !std::isfinite(G.dt))
+    return fail(FWI_EINVAL, "dx and dt must be positive");
+  if (!(G.kappa_max >= 0.f) || !(G.kappa_max < 0.5f))
+    return fail(FWI_EINVAL, "kappa_max must be in [0, 0.5)");
+  if (G.ckpt_every < 1) return fail(FWI_EINVAL, "ckpt_every must be >= 1");
+  if (!G.src_zx || !G.rec_zx || !G.wavelet) return fail(FWI_EINVAL, "null geometry array");
+  if (!(G.inv_noise_var >= 0.0) || !std::isfinite(G.inv_noise_var))
+    return fail(FWI_EINVAL, "inv_noise_var must be finite and >= 0");
+  const long long nzp = (long long)G.nz + 2 * G.nb, nxp = (long long)G.nx + 2 * G.nb;
+  if (nzp > 65536 || nxp > 65536) return fail(FWI_EINVAL, "padded grid too large");
+  for (int s = 0; s < G.ns; ++s) {
+    const int iz = G.src_zx[2 * s], ix = G.src_zx[2 * s + 1];
+    if (iz < 0 || iz >= G.nz || ix < 0 || ix >= G.nx)
+      return fail(FWI_EINVAL, "source " + std::to_string(s) + " outside the model grid");
+  }
+  for (int r = 0; r < G.nr; ++r) {
+    const int iz = G.rec_zx[2 * r], ix = G.rec_zx[2 * r + 1];
+    if (iz < 0 || iz >= G.nz || ix < 0 || ix >= G.nx)
+      return fail(FWI_EINVAL, "receiver " + std::to_string(r) + " outside the model grid");
+  }
+  for (int n = 0; n < G.nt; ++n)
+    if (!std::isfinite(G.wavelet[n])) return fail(FWI_EINVAL, "wavelet not finite");
+
+  fwi_plan *p = new fwi_plan();
+  Geo &g = p->geo;
+  g.nz = G.nz;
+  g.nx = G.nx;
+  g.nb = G.nb;
+  g.nzp = (int)nzp;
+  g.nxp = (int)nxp;
+  g.pitch = (int)((nxp + TX - 1) / TX * TX);
+  g.tiles_x = g.pitch / TX;
+  g.tiles_z = (int)((nzp + TZ - 1) / TZ);
+  g.ntiles = g.tiles_x * g.tiles_z;
+  g.ns = G.ns;
+  g.nt = G.nt;
+  g.nr = G.nr;
+  g.fs = (long long)g.tiles_z * TZ * g.pitch;
+  g.kmax = G.kappa_max;
+  g.inv_nb = G.nb > 0 ? 1.0f / (float)G.nb : 0.0f;
+  const double h2 = (double)G.dx * (double)G.dx;
+  // centred 8th-order second-difference weights (the centre weight -205/72
+  // is implied: the kernels difference neighbours against the centre)
+  g.c1 = (float)((8.0 / 5.0) / h2);
+  g.c2 = (float)((-1.0 / 5.0) / h2);
+  g.c3 = (float)((8.0 / 315.0) / h2);
+  g.c4 = (float)((-1.0 / 560.0) / h2);
+  g.dt = G.dt;
+  g.inv_dx = 1.0f / G.dx;
+  p->dx = G.dx;
+  p->dt = G.dt;
+  p->K = std::min(G.ckpt_every, G.nt - 1);
+  p->nseg = (G.nt - 1 + p->K - 1) / p->K;
+  p->inv_noise_var = G.inv_noise_var;
+  p->wavelet.assign(G.wavelet, G.wavelet + G.nt);
+  if (const char *e = std::getenv("FWI_ADJ_GROUP")) p->adj_group_override = std::atoi(e);
+
+  // receiver tables: sort receivers by (tile, local index, number)
+  std::vector<std::tuple<int, int, int, long long>> recs;  // tile, local, id, gidx
+  for (int r = 0; r < G.nr; ++r) {
+    const int i = G.rec_zx[2 * r] + G.nb, j = G.rec_zx[2 * r + 1] + G.nb;
+    const int tile = (i / TZ) * g.tiles_x + j / TX;
+    const int local = (i % TZ) * TX + j % TX;
+    recs.emplace_back(tile, local, r, (long long)i * g.pitch + j);
+  }
+  std::sort(recs.begin(), recs.end());
+  std::vector<int> trp(g.ntiles + 1, 0), rloc, rid, tnp(g.ntiles + 1, 0), nloc, ngidx, nrp,
+      nrec;
+  for (auto &e : recs) {
+    trp[std::get<0>(e) + 1]++;
+    rloc.push_back(std::get<1>(e));
+    rid.push_back(std::get<2>(e));
+  }
+  for (int t = 0; t < g.ntiles; ++t) trp[t + 1] += trp[t];
+  for (size_t q = 0; q < recs.size(); ++q) {
+    const bool fresh = q == 0 || std::get<0>(recs[q]) != std::get<0>(recs[q - 1]) ||
+                       std::get<1>(recs[q]) != std::get<1>(recs[q - 1]);
+    if (fresh) {
+      tnp[std::get<0>(recs[q]) + 1]++;
+      nloc.push_back(std::get<1>(recs[q]));
+      ngidx.push_back((int)std::get<3>(recs[q]));
+      nrp.push_back((int)nrec.size());
+    }
+    nrec.push_back(std::get<2>(recs[q]));
+  }
+  nrp.push_back((int)nrec.size());
+  for (int t = 0; t < g.ntiles; ++t) tnp[t + 1] += tnp[t];
+  if ((long long)g.fs > 2147483647LL) {
+    delete p;
+    return fail(FWI_EINVAL, "padded field too large for 32-bit node indices");
+  }
+
+  // device block image
+  auto &b = p->blk;
+  auto put = [&](const std::vector<int> &v) {
+    const size_t at = b.size();
+    b.insert(b.end(), v.begin(), v.end());
+    b.resize((b.size() + 63) / 64 * 64, 0);
+    return at;
+  };
+  p->off_status = put(std::vector<int>(1, 0));
+  std::vector<int> src(2 * G.ns);
+  for (int s = 0; s < G.ns; ++s) {
+    src[2 * s] = G.src_zx[2 * s] + G.nb;
+    src[2 * s + 1] = G.src_zx[2 * s + 1] + G.nb;
+  }
+  p->off_src = put(src);
+  p->off_trp = put(trp);
+  p->off_rloc = put(rloc);
+  p->off_rid = put(rid);
+  p->off_tnp = put(tnp);
+  p->off_nloc = put(nloc);
+  p->off_ngidx = put(ngidx);
+  p->off_nrp = put(nrp);
+  p->off_nrec = put(nrec);
+  *out = p;
+  return FWI_OK;
+}
+
+void fwi_plan_destroy(fwi_plan *p) { delete p; }
+
+int fwi_plan_device_bytes(const fwi_plan *p, size_t *bytes) {
+  if (!p || !bytes) return fail(FWI_EINVAL, "null argument");
+  *bytes = p->blk.size() * sizeof(int);
+  return FWI_OK;
+}
+
+int fwi_plan_dims(const fwi_plan *p, int32_t dims[6]) {
+  if (!p || !dims) return fail(FWI_EINVAL, "null argument");
+  dims[0] = p->geo.nzp;
+  dims[1] = p->geo.nxp;
+  dims[2] = p->geo.pitch;
+  dims[3] = p->geo.tiles_z;
+  dims[4] = p->geo.tiles_x;
+  dims[5] = p->K;
+  return FWI_OK;
+}
+
+int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream) {
+  if (!p || !dev) return fail(FWI_EINVAL, "null argument");
+  if (bytes < p->blk.size() * sizeof(int))
+    return fail(FWI_ENOMEM, "device block too small");
+  if (reinterpret_cast<uintptr_t>(dev) % ALIGN)
+    return fail(FWI_EINVAL, "device block must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIP_TRY(hipMemcpyAsync(dev, p->blk.data(), p->blk.size() * sizeof(int), hipMemcpyHostToDevice,
+                         st));
+  HIP_TRY(hipStreamSynchronize(st));
+  p->dev = dev;
+  int *base = static_cast<int *>(dev);
+  DevTables &t = p->tabs;
+  t.status = reinterpret_cast<unsigned int *>(base + p->off_status);
+  t.src_ij = base + p->off_src;
+  t.tile_rec_ptr = base + p->off_trp;
+  t.rec_local = base + p->off_rloc;
+  t.rec_id = base + p->off_rid;
+  t.tile_node_ptr = base + p->off_tnp;
+  t.node_local = base + p->off_nloc;
+  t.node_gidx = base + p->off_ngidx;
+  t.node_rec_ptr = base + p->off_nrp;
+  t.node_recs = base + p->off_nrec;
+  return FWI_OK;
+}
+
+int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes) {
+  if (!p || !bytes) return fail(FWI_EINVAL, "null argument");
+  if (op < FWI_OP_FORWARD || op > FWI_OP_GN_HVP) return fail(FWI_EINVAL, "unknown op");
+  if (batch < 1 || batch > 4096) return fail(FWI_EINVAL, "batch must be in [1, 4096]");
+  *bytes = layout(p, op, batch).total;
+  return FWI_OK;
+}
+
+int fwi_forward(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_bytes,
+                void *stream) {
+  if (int rc = check_call(p, FWI_OP_FORWARD, 1, ws, ws_bytes)) return rc;
+  if (!m || !d) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_FORWARD, 1);
+  const Geo &g = p->geo;
+  if (int rc = prologue(p, L, ws, m, nullptr, 0, false, false, st)) return rc;
+  HIP_TRY(launch_zero_t0(d, g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, 1, false, d, nullptr, false, st)) return rc;
+  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_born(fwi_plan *p, const float *m, const float *v, int B, float *dd, void *ws,
+             size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_BORN, B, ws, ws_bytes)) return rc;
+  if (!m || !v || !dd) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_BORN, B);
+  const Geo &g = p->geo;
+  if (int rc = prologue(p, L, ws, m, v, B, true, false, st)) return rc;
+  HIP_TRY(launch_zero_t0(dd, B * g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, B, true, nullptr, dd, false, st)) return rc;
+  HIP_TRY(launch_check_finite(dd, (long long)B * g.ns * g.nt * g.nr, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *gout, void *ws,
+                size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_ADJOINT, B, ws, ws_bytes)) return rc;
+  if (!m || !r || !gout) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_ADJOINT, B);
+  const Geo &g = p->geo;
+  if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
+  if (int rc = forward_sweep(p, L, ws, 1, false, nullptr, nullptr, true, st)) return rc;
+  if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 1.0, gout, st));
+  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi, float *gout,
+                    void *ws, size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_MISFIT_GRAD, 1, ws, ws_bytes)) return rc;
+  if (!m || !dobs || !phi || !gout) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_MISFIT_GRAD, 1);
+  const Geo &g = p->geo;
+  float *dres = at<float>(ws, L.dres);
+  if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
+  HIP_TRY(launch_zero_t0(dres, g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, 1, false, dres, nullptr, true, st)) return rc;
+  HIP_TRY(launch_residual(dres, dobs, (long long)g.ns * g.nt * g.nr, at<double>(ws, L.part),
+                          NPARTS, 0.5 * p->inv_noise_var, phi, st));
+  if (int rc = reverse_sweep(p, L, ws, 1, dres, st)) return rc;
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, 1, p->inv_noise_var, gout, st));
+  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, void *ws,
+               size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_GN_HVP, B, ws, ws_bytes)) return rc;
+  if (!m || !v || !hv) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_GN_HVP, B);
+  const Geo &g = p->geo;
+  float *dd = at<float>(ws, L.dd);
+  if (int rc = prologue(p, L, ws, m, v, B, true, true, st)) return rc;
+  HIP_TRY(launch_zero_t0(dd, B * g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, B, true, nullptr, dd, true, st)) return rc;
+  if (int rc = reverse_sweep(p, L, ws, B, dd, st)) return rc;
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, p->inv_noise_var, hv, st));
+  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_status(fwi_plan *p, void *stream, uint32_t *status) {
+  if (!p || !status) return fail(FWI_EINVAL, "null argument");
+  if (!p->dev) return fail(FWI_EUNBOUND, "plan has no device block");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned int v = 0, zero = 0;
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(&v, p->tabs.status, sizeof(v), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(p->tabs.status, &zero, sizeof(zero), hipMemcpyHostToDevice));
+  *status = v;
+  return FWI_OK;
+}
+
+}  // extern "C"

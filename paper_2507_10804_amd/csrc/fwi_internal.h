@@ -1,0 +1,83 @@
+// Internal definitions shared by the host plan code and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace fwi {
+
+// Tile of one workgroup: 64 columns (one wavefront wide) by TZ rows; each of
+// the NWAVE wavefronts owns RZ consecutive rows of every column.
+constexpr int TX = 64;
+constexpr int NWAVE = 4;
+constexpr int RZ = 8;
+constexpr int TZ = NWAVE * RZ;
+constexpr int HALO = 4;          // 8th-order stencil radius
+constexpr int LW = TX + 2 * HALO;  // LDS row width
+constexpr int LH = TZ + 2 * HALO;  // LDS rows
+constexpr int NTHREADS = TX * NWAVE;
+
+// Largest Courant number max(m) dt/dx the scheme tolerates.
+constexpr float CFL_LIMIT = 0.5546f;
+
+// Geometry of the padded grid as the kernels see it.  Every per-point array
+// (wavefields, coefficients, images) uses the same layout: element (i, j) of
+// the padded grid at i*pitch + j, pitch a multiple of 64 floats and at least
+// NXp, rows rounded up to whole tiles; `fs` is the element count of one
+// such array.
+struct Geo {
+  int nz, nx, nb;
+  int nzp, nxp, pitch;
+  int tiles_x, tiles_z, ntiles;
+  int ns, nt, nr;
+  long long fs;
+  float kmax, inv_nb;
+  float c1, c2, c3, c4;  // C1..C4 of the stencil, divided by dx^2 (C0 = -2 sum)
+  float dt, inv_dx;
+};
+
+// Device block of a plan (offsets in int32 units from its base).
+struct DevTables {
+  const int *src_ij;        // ns x (i, j) padded coordinates
+  const int *tile_rec_ptr;  // ntiles+1: receivers of tile t in [ptr[t], ptr[t+1])
+  const int *rec_local;     // local index lz*TX + lx of each listed receiver
+  const int *rec_id;        // receiver number of each listed receiver
+  const int *tile_node_ptr; // ntiles+1: distinct receiver nodes of a tile
+  const int *node_local;    // local index of each node
+  const int *node_gidx;     // i*pitch + j of each node
+  const int *node_rec_ptr;  // nnodes+1: receivers sitting on node k
+  const int *node_recs;     // receiver numbers, grouped by node
+  unsigned int *status;     // FWI_STATUS_* bits
+};
+
+// Arguments of one forward / forward+Born time step.
+struct StepArgs {
+  const float *c;     // [fs] (dt m_pad)^2 / (1 + kappa)
+  const float *dc;    // [B][fs] Born coefficient perturbation, or null
+  float *u;           // [ns][2][fs]: u^k lives in slot k & 1
+  float *du;          // [ns][B][2][fs] Born wavefields, same slot rule
+  float *w_out;       // [ns][fs]: receives w^n = L u^n + f^n, or null
+  float *d_out;       // [ns][nt][nr]: receives R u^{n+1}, or null
+  float *dd_out;      // [B][ns][nt][nr]: receives R du^{n+1}, or null
+  float *ck;          // [ns][2][fs] checkpoint slot: u^{n+1}, u^n, or null
+  int n;              // step: computes u^{n+1}
+  int B;
+  float src_amp;      // s(n dt) / dx^2
+};
+
+// Arguments of one adjoint + imaging time step (mu = c * lambda form).
+struct AdjArgs {
+  const float *c;     // [fs]
+  const float *s2m;   // [fs] 2 / m_pad
+  float *mu;          // [B][ns][2][fs]: mu^k in slot k & 1
+  const float *w;     // [ns][fs] w^k for this step, or null (no image term)
+  const float *r;     // [B][ns][nt][nr] data injected at the receivers
+  double *img;        // [G][B][fs] partial images, one per shot group
+  int k;              // computes mu^k
+  int B;
+  int group;          // shots per workgroup
+  int ngroups;
+};
+
+}  // namespace fwi

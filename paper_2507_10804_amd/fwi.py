@@ -1,0 +1,236 @@
+"""Thin ctypes binding of the C ABI in ``include/fwi.h``.
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels of ``libfwi_mi355x.so``.  PyTorch supplies device memory (plan block,
+workspaces, outputs) and the stream each call is enqueued on.  There is no
+CPU fallback: if the library is missing or no GPU is present, calls fail.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfwi_mi355x.so")
+
+FWI_OP_FORWARD, FWI_OP_BORN, FWI_OP_ADJOINT, FWI_OP_MISFIT_GRAD, FWI_OP_GN_HVP = range(5)
+STATUS_BAD_MODEL, STATUS_CFL, STATUS_NONFINITE = 1, 2, 4
+
+EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_device_bytes",
+           "fwi_plan_bind", "fwi_workspace_size", "fwi_plan_dims", "fwi_forward", "fwi_born",
+           "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
+           "fwi_last_error"]
+
+
+class FwiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"fwi error {code}: {msg}")
+        self.code = code
+
+
+class _Geometry(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("nz", ctypes.c_int32), ("nb", ctypes.c_int32),
+                ("nt", ctypes.c_int32), ("dx", ctypes.c_float), ("dt", ctypes.c_float),
+                ("kappa_max", ctypes.c_float), ("ns", ctypes.c_int32),
+                ("src_zx", ctypes.c_void_p), ("nr", ctypes.c_int32),
+                ("rec_zx", ctypes.c_void_p), ("wavelet", ctypes.c_void_p),
+                ("ckpt_every", ctypes.c_int32), ("inv_noise_var", ctypes.c_double)]
+
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the in-tree HIP library (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise FwiError(-4, f"{path} not built: run __graft_entry__.build()")
+        lib = ctypes.CDLL(path)
+        P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        sig = {
+            "fwi_abi_version": ([], I),
+            "fwi_plan_create": ([P, P], I),
+            "fwi_plan_destroy": ([P], None),
+            "fwi_plan_device_bytes": ([P, P], I),
+            "fwi_plan_bind": ([P, P, Z, P], I),
+            "fwi_workspace_size": ([P, I, I, P], I),
+            "fwi_plan_dims": ([P, P], I),
+            "fwi_forward": ([P, P, P, P, Z, P], I),
+            "fwi_born": ([P, P, P, I, P, P, Z, P], I),
+            "fwi_adjoint": ([P, P, P, I, P, P, Z, P], I),
+            "fwi_misfit_grad": ([P, P, P, P, P, P, Z, P], I),
+            "fwi_gn_hvp": ([P, P, P, I, P, P, Z, P], I),
+            "fwi_status": ([P, P, P], I),
+            "fwi_strerror": ([I], ctypes.c_char_p),
+            "fwi_last_error": ([], ctypes.c_char_p),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = lib
+        return lib
+
+
+def _check(rc):
+    if rc != 0:
+        lib = load_library()
+        raise FwiError(rc, f"{lib.fwi_strerror(rc).decode()}: {lib.fwi_last_error().decode()}")
+
+
+def _geometry_struct(geom):
+    keep = dict(src=np.ascontiguousarray(geom.src_zx, dtype=np.int32),
+                rec=np.ascontiguousarray(geom.rec_zx, dtype=np.int32),
+                wav=np.ascontiguousarray(geom.wavelet[: geom.nt], dtype=np.float32))
+    g = _Geometry(nx=geom.nx, nz=geom.nz, nb=geom.nb, nt=geom.nt, dx=geom.dx, dt=geom.dt,
+                  kappa_max=geom.kappa_max, ns=keep["src"].shape[0],
+                  src_zx=keep["src"].ctypes.data, nr=keep["rec"].shape[0],
+                  rec_zx=keep["rec"].ctypes.data, wavelet=keep["wav"].ctypes.data,
+                  ckpt_every=int(geom.ckpt_every), inv_noise_var=float(geom.inv_noise_var))
+    return g, keep
+
+
+class Plan:
+    """One acquisition geometry bound to one GPU.
+
+    Methods take and return float32 CUDA tensors (model space [B][nz][nx],
+    data space [B][ns][nt][nr]) and enqueue on the current torch stream.
+    Workspaces are cached per (operation, batch); a Plan is not thread-safe.
+    """
+
+    def __init__(self, geom, device=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load_library()
+        self.geom = geom
+        self.device = torch.device(device if device is not None else "cuda")
+        g, keep = _geometry_struct(geom)
+        h = ctypes.c_void_p()
+        _check(self.lib.fwi_plan_create(ctypes.byref(g), ctypes.byref(h)))
+        self._h = h
+        nb = ctypes.c_size_t()
+        _check(self.lib.fwi_plan_device_bytes(h, ctypes.byref(nb)))
+        self._blk = torch.zeros(max(nb.value, 256), dtype=torch.uint8, device=self.device)
+        _check(self.lib.fwi_plan_bind(h, ctypes.c_void_p(self._blk.data_ptr()), nb.value,
+                                      self._stream()))
+        self._ws = {}
+        dims = (ctypes.c_int32 * 6)()
+        _check(self.lib.fwi_plan_dims(h, dims))
+        self.nzp, self.nxp, self.pitch, self.tiles_z, self.tiles_x, self.K = list(dims)
+
+    # -- plumbing ---------------------------------------------------------
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.fwi_plan_destroy(h)
+            self._h = None
+
+    def _stream(self):
+        return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def workspace_bytes(self, op, batch=1):
+        n = ctypes.c_size_t()
+        _check(self.lib.fwi_workspace_size(self._h, int(op), int(batch), ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, op, batch=1):
+        key = (int(op), int(batch))
+        ws = self._ws.get(key)
+        if ws is None:
+            nbytes = self.workspace_bytes(op, batch)
+            ws = self.torch.empty(nbytes, dtype=self.torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def release_workspaces(self):
+        self._ws.clear()
+
+    def _in(self, x, shape_tail, name):
+        t = self.torch
+        if not isinstance(x, t.Tensor) or x.device.type != "cuda" or x.dtype != t.float32:
+            raise TypeError(f"{name} must be a float32 CUDA tensor")
+        x = x.contiguous()
+        if tuple(x.shape[-len(shape_tail):]) != tuple(shape_tail):
+            raise ValueError(f"{name} has shape {tuple(x.shape)}, expected (..., {shape_tail})")
+        return x
+
+    @staticmethod
+    def _p(x):
+        return ctypes.c_void_p(x.data_ptr())
+
+    # -- operations -------------------------------------------------------
+    def forward(self, m):
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        d = self.torch.empty((g.ns, g.nt, g.nr), dtype=self.torch.float32, device=self.device)
+        ws = self.workspace(FWI_OP_FORWARD)
+        _check(self.lib.fwi_forward(self._h, self._p(m), self._p(d), self._p(ws), ws.numel(),
+                                    self._stream()))
+        return d
+
+    def born(self, m, v):
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        v = self._in(v, (g.nz, g.nx), "v")
+        single = v.dim() == 2
+        v = v.reshape(-1, g.nz, g.nx)
+        B = v.shape[0]
+        dd = self.torch.empty((B, g.ns, g.nt, g.nr), dtype=self.torch.float32, device=self.device)
+        ws = self.workspace(FWI_OP_BORN, B)
+        _check(self.lib.fwi_born(self._h, self._p(m), self._p(v), B, self._p(dd), self._p(ws),
+                                 ws.numel(), self._stream()))
+        return dd[0] if single else dd
+
+    def adjoint(self, m, r):
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        r = self._in(r, (g.ns, g.nt, g.nr), "r")
+        single = r.dim() == 3
+        r = r.reshape(-1, g.ns, g.nt, g.nr)
+        B = r.shape[0]
+        out = self.torch.empty((B, g.nz, g.nx), dtype=self.torch.float32, device=self.device)
+        ws = self.workspace(FWI_OP_ADJOINT, B)
+        _check(self.lib.fwi_adjoint(self._h, self._p(m), self._p(r), B, self._p(out),
+                                    self._p(ws), ws.numel(), self._stream()))
+        return out[0] if single else out
+
+    def misfit_grad(self, m, dobs):
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        dobs = self._in(dobs, (g.ns, g.nt, g.nr), "dobs")
+        phi = self.torch.empty((), dtype=self.torch.float64, device=self.device)
+        grad = self.torch.empty((g.nz, g.nx), dtype=self.torch.float32, device=self.device)
+        ws = self.workspace(FWI_OP_MISFIT_GRAD)
+        _check(self.lib.fwi_misfit_grad(self._h, self._p(m), self._p(dobs), self._p(phi),
+                                        self._p(grad), self._p(ws), ws.numel(),
+                                        self._stream()))
+        return phi, grad
+
+    def gn_hvp(self, m, v, out=None):
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        v = self._in(v, (g.nz, g.nx), "v")
+        single = v.dim() == 2
+        v = v.reshape(-1, g.nz, g.nx)
+        B = v.shape[0]
+        hv = out if out is not None else self.torch.empty((B, g.nz, g.nx),
+                                                          dtype=self.torch.float32,
+                                                          device=self.device)
+        ws = self.workspace(FWI_OP_GN_HVP, B)
+        _check(self.lib.fwi_gn_hvp(self._h, self._p(m), self._p(v), B, self._p(hv),
+                                   self._p(ws), ws.numel(), self._stream()))
+        return hv[0] if single else hv
+
+    def status(self):
+        """Synchronise, return and clear the device status bits."""
+        st = ctypes.c_uint32()
+        _check(self.lib.fwi_status(self._h, self._stream(), ctypes.byref(st)))
+        return st.value

@@ -85,8 +85,11 @@ def ricker(nt: int, dt: float, f0: float, t0: float | None = None) -> np.ndarray
 
 
 def sponge_strength(cfl: float, nb: int) -> float:
-    """Peak damping of the absorbing layer, 3*C*ln(1e3)/(2*nb)."""
-    return 3.0 * cfl * math.log(1.0e3) / (2.0 * nb)
+    """Peak damping of the absorbing layer, 3*C*ln(1e3)/(2*nb), capped at
+    0.45 so that corner cells (twice the peak) keep a damping below 1."""
+    if nb <= 0:
+        return 0.0
+    return min(3.0 * cfl * math.log(1.0e3) / (2.0 * nb), 0.45)
 
 
 def surface_shots(nx: int, ns: int, iz: int = 1) -> np.ndarray:

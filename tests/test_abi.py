@@ -1,0 +1,101 @@
+"""C-ABI checks that need no GPU: the library loads, exports every symbol the
+header declares, and its host-side plan logic validates arguments and sizes
+workspaces (no compute call is made here)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2507_10804_amd import fwi, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fwi.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return fwi.load_library()
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fwi_[a-z_]+)\s*\(", text)))
+
+
+def test_header_matches_binding():
+    assert declared_functions() == sorted(fwi.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.fwi_abi_version() == 1
+
+
+def _plan(lib, geom):
+    g, keep = fwi._geometry_struct(geom)
+    h = ctypes.c_void_p()
+    rc = lib.fwi_plan_create(ctypes.byref(g), ctypes.byref(h))
+    return rc, h, keep
+
+
+def test_plan_host_logic(lib):
+    geom, _, _ = synth.config_small()
+    rc, h, _ = _plan(lib, geom)
+    assert rc == 0
+    dims = (ctypes.c_int32 * 6)()
+    assert lib.fwi_plan_dims(h, dims) == 0
+    nzp, nxp, pitch, tz, tx, K = list(dims)
+    assert (nzp, nxp) == (168, 168)
+    assert pitch % 64 == 0 and pitch >= nxp and tx == pitch // 64 and tz * 32 >= nzp
+    assert K == 50
+    nb = ctypes.c_size_t()
+    assert lib.fwi_plan_device_bytes(h, ctypes.byref(nb)) == 0 and nb.value > 0
+    sizes = {}
+    for op in range(5):
+        for B in (1, 4):
+            n = ctypes.c_size_t()
+            assert lib.fwi_workspace_size(h, op, B, ctypes.byref(n)) == 0
+            sizes[op, B] = n.value
+            assert n.value % 256 == 0
+    # batched operations need more memory, single-vector ones do not change
+    assert sizes[fwi.FWI_OP_GN_HVP, 4] > sizes[fwi.FWI_OP_GN_HVP, 1]
+    assert sizes[fwi.FWI_OP_FORWARD, 4] == sizes[fwi.FWI_OP_FORWARD, 1]
+    n = ctypes.c_size_t()
+    assert lib.fwi_workspace_size(h, 9, 1, ctypes.byref(n)) == fwi.FWI_OP_FORWARD - 1
+    # a compute call on an unbound plan is refused before touching the GPU
+    rc = lib.fwi_forward(h, None, None, None, 0, None)
+    assert rc == -6
+    assert b"fwi_plan_bind" in lib.fwi_last_error()
+    lib.fwi_plan_destroy(h)
+
+
+@pytest.mark.parametrize("field,value,needle", [
+    ("nt", 1, b"nt"),
+    ("dx", 0.0, b"dx"),
+    ("kappa_max", 0.7, b"kappa_max"),
+    ("ckpt_every", 0, b"ckpt_every"),
+    ("src", [[0, 200]], b"source 0"),
+    ("rec", [[-1, 3]], b"receiver 0"),
+    ("nb", -1, b"nb"),
+])
+def test_plan_rejects_bad_geometry(lib, field, value, needle):
+    geom, _, _ = synth.config_small()
+    if field == "src":
+        geom.src_zx = np.array(value, dtype=np.int32)
+    elif field == "rec":
+        geom.rec_zx = np.array(value, dtype=np.int32)
+    else:
+        setattr(geom, field, value)
+    rc, h, _ = _plan(lib, geom)
+    assert rc == -1
+    assert needle in lib.fwi_last_error()
+    assert not h.value
+
+
+def test_strerror(lib):
+    for code in (0, -1, -2, -3, -4, -5, -6, -99):
+        assert isinstance(lib.fwi_strerror(code), bytes)

@@ -1,0 +1,239 @@
+"""GPU parity: the HIP path (FP32, through the C ABI) against the FP64 oracle
+on the same seeded inputs, plus the identities that hold on the GPU alone.
+
+Tolerances (relative L2 per output): forward and Born data 1e-5, migration
+and gradient 1e-4, Gauss-Newton H v 1e-4; dot-product test and Hessian
+symmetry 1e-5.  FP32 storage and arithmetic give ~1e-7 per operation; over
+hundreds to thousands of leapfrog steps the rounding grows to ~1e-6..1e-5,
+leaving an order of margin below the Hessian target.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_10804_amd import synth
+from tests._cases import rel, tiny
+
+pytestmark = pytest.mark.gpu
+
+TOL_DATA = 1e-5
+TOL_IMAGE = 1e-4
+TOL_DOT = 1e-5
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def dev(torch, x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32), device="cuda")
+
+
+def host(x):
+    return x.detach().double().cpu().numpy()
+
+
+def make_plan(geom):
+    from paper_2507_10804_amd import fwi
+    return fwi.Plan(geom)
+
+
+# ------------------------------------------------------------ small config
+
+@pytest.fixture(scope="module")
+def small(torch):
+    g, m_true, m_eval = synth.config_small()
+    say("case: 128x128, 4 shots, 32 receivers, nt=500; oracle reference")
+    dobs = oracle.forward(g, m_true)
+    v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
+    return dict(g=g, m_true=m_true, m=m_eval, dobs=dobs, v=v, plan=make_plan(g))
+
+
+def test_small_forward(torch, small):
+    say("entry: fwi_forward small")
+    d = host(small["plan"].forward(dev(torch, small["m_true"])))
+    torch.cuda.synchronize()
+    assert small["plan"].status() == 0
+    assert rel(d, small["dobs"]) < TOL_DATA
+
+
+def test_small_born(torch, small):
+    say("entry: fwi_born small")
+    g, m, v = small["g"], small["m"], small["v"]
+    dd = host(small["plan"].born(dev(torch, m), dev(torch, v)))
+    assert rel(dd, oracle.born(g, m, v)) < TOL_DATA
+
+
+def test_small_adjoint(torch, small):
+    say("entry: fwi_adjoint small")
+    g, m = small["g"], small["m"]
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=2)
+    out = host(small["plan"].adjoint(dev(torch, m), dev(torch, r)))
+    assert rel(out, oracle.adjoint(g, m, r)) < TOL_IMAGE
+
+
+def test_small_misfit_grad(torch, small):
+    say("entry: fwi_misfit_grad small")
+    g, m, dobs = small["g"], small["m"], small["dobs"]
+    phi, grad = small["plan"].misfit_grad(dev(torch, m), dev(torch, dobs))
+    phi_o, grad_o = oracle.misfit_grad(g, m, dobs)
+    # the residual d - dobs is a difference of close data sets, so the data
+    # tolerance is amplified by |d| / |d - dobs| in Phi
+    amp = np.linalg.norm(dobs) / np.linalg.norm(oracle.forward(g, m) - dobs)
+    assert float(phi) == pytest.approx(phi_o, rel=2 * TOL_DATA * amp)
+    assert rel(host(grad), grad_o) < TOL_IMAGE
+
+
+def test_small_gn_hvp(torch, small):
+    say("entry: fwi_gn_hvp small B=1")
+    g, m, v = small["g"], small["m"], small["v"]
+    hv = host(small["plan"].gn_hvp(dev(torch, m), dev(torch, v)))
+    e = rel(hv, oracle.gn_hvp(g, m, v))
+    say(f"  rel-L2 Hv small = {e:.3e}")
+    assert e < TOL_IMAGE
+
+
+# ------------------------------------------------------- identities on GPU
+
+def test_dot_product_gpu(torch, small):
+    say("entry: fwi_born + fwi_adjoint dot test small")
+    g, m, v = small["g"], small["m"], small["v"]
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=3)
+    p = small["plan"]
+    jv = host(p.born(dev(torch, m), dev(torch, v)))
+    jtr = host(p.adjoint(dev(torch, m), dev(torch, r)))
+    lhs, rhs = np.vdot(jv, r), np.vdot(v, jtr)
+    assert abs(lhs - rhs) <= TOL_DOT * abs(lhs)
+
+
+def test_hessian_symmetry_gpu(torch, small):
+    say("entry: fwi_gn_hvp B=2 symmetry small")
+    g, m, v = small["g"], small["m"], small["v"]
+    u = synth.smooth_random((g.nz, g.nx), seed=7, sigma=5.0)
+    hv = host(small["plan"].gn_hvp(dev(torch, m), dev(torch, np.stack([v, u]))))
+    a, b = np.vdot(u, hv[0]), np.vdot(hv[1], v)
+    assert abs(a - b) <= TOL_DOT * abs(a)
+    assert np.vdot(v, hv[0]) > 0 and np.vdot(u, hv[1]) > 0
+
+
+def test_batched_equals_looped_and_deterministic(torch, small):
+    say("entry: fwi_gn_hvp B=3 vs 3 x B=1, repeat")
+    g, m = small["g"], small["m"]
+    vs = synth.smooth_random_batch(g.nz, g.nx, seeds=[21, 22, 23])
+    p = small["plan"]
+    mb = dev(torch, m)
+    hb = host(p.gn_hvp(mb, dev(torch, vs)))
+    hb2 = host(p.gn_hvp(mb, dev(torch, vs)))
+    assert np.array_equal(hb, hb2), "two identical calls differ"
+    for i in range(3):
+        assert rel(hb[i], host(p.gn_hvp(mb, dev(torch, vs[i])))) < 1e-6
+
+
+def test_checkpoint_interval_invariance(torch):
+    g, m = tiny(nt=230)
+    v = synth.smooth_random(m.shape, seed=1, sigma=3.0)
+    outs = []
+    for K in (1, 7, 50, 229, 5000):
+        say(f"entry: fwi_gn_hvp tiny K={K}")
+        g.ckpt_every = K
+        p = make_plan(g)
+        outs.append(host(p.gn_hvp(dev(torch, m), dev(torch, v))))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+    assert rel(outs[0], oracle.gn_hvp(g, m, v)) < TOL_IMAGE
+
+
+# ------------------------------------------------------------- edge cases
+
+def _parity_all(torch, g, m, tol_img=TOL_IMAGE):
+    v = synth.smooth_random(m.shape, seed=1, sigma=2.0)
+    p = make_plan(g)
+    mb = dev(torch, m)
+    assert rel(host(p.forward(mb)), oracle.forward(g, m)) < TOL_DATA
+    assert rel(host(p.born(mb, dev(torch, v))), oracle.born(g, m, v)) < TOL_DATA
+    assert rel(host(p.gn_hvp(mb, dev(torch, v))), oracle.gn_hvp(g, m, v)) < tol_img
+    assert p.status() == 0
+
+
+def test_ragged_tiles_and_sponge(torch):
+    say("case: tiny 48x40 nb=10 ragged tiles")
+    g, m = tiny(nt=200)
+    _parity_all(torch, g, m)
+
+
+def test_no_sponge_and_corner_source(torch):
+    say("case: nb=0, source and receivers at corners")
+    g, m = tiny(nx=70, nz=33, nt=120, nb=0)
+    g.src_zx = np.array([[0, 0], [32, 69], [16, 35]], dtype=np.int32)
+    g.rec_zx = np.array([[0, 69], [32, 0], [0, 0], [16, 36]], dtype=np.int32)
+    _parity_all(torch, g, m)
+
+
+def test_grid_smaller_than_tile(torch):
+    say("case: 5x3 model, nb=2")
+    m = np.array([[2000.0, 2100, 2200, 2050, 1990]] * 3) + np.arange(3)[:, None] * 30
+    g = synth.make_geometry(5, 3, nt=40, ns=2, rec_ix=[0, 4], f0=60.0, v_nominal=2300.0, nb=2)
+    _parity_all(torch, g, m)
+
+
+def test_duplicate_receivers_and_tile_edges(torch):
+    say("case: receivers duplicated and on tile boundaries")
+    g, m = tiny(nx=150, nz=50, nt=150, nb=10)
+    # padded columns 63/64 and 127/128 straddle tile boundaries (nb = 10)
+    ix = np.array([53, 54, 54, 117, 118, 118, 0, 149])
+    g.rec_zx = np.stack([np.array([1, 1, 1, 21, 22, 22, 49, 0]), ix], 1).astype(np.int32)
+    _parity_all(torch, g, m)
+
+
+def test_two_steps_only(torch):
+    say("case: nt=2")
+    g, m = tiny(nt=2)
+    v = synth.smooth_random(m.shape, seed=1, sigma=2.0)
+    p = make_plan(g)
+    d = host(p.forward(dev(torch, m)))
+    assert np.allclose(d, oracle.forward(g, m), atol=1e-12, rtol=1e-5)
+    hv = host(p.gn_hvp(dev(torch, m), dev(torch, v)))
+    ho = oracle.gn_hvp(g, m, v)
+    assert np.allclose(hv, ho, atol=1e-7 * max(np.abs(ho).max(), 1e-30))
+
+
+def test_status_flags(torch):
+    from paper_2507_10804_amd import fwi
+    say("case: status word for bad model and CFL")
+    g, m = tiny(nt=20)
+    p = make_plan(g)
+    bad = m.copy()
+    bad[3, 4] = -1.0
+    p.forward(dev(torch, bad))
+    assert p.status() & fwi.STATUS_BAD_MODEL
+    fast = m * 1.6  # Courant number 0.4 * 2300 * 1.6 / 2300 > 0.5546
+    p.forward(dev(torch, fast))
+    assert p.status() & fwi.STATUS_CFL
+    p.forward(dev(torch, m))
+    assert p.status() == 0
+
+
+def test_argument_errors(torch):
+    from paper_2507_10804_amd import fwi
+    g, m = tiny(nt=20)
+    p = make_plan(g)
+    with pytest.raises(ValueError):
+        p.forward(dev(torch, m[:-1]))
+    with pytest.raises(TypeError):
+        p.forward(torch.zeros(m.shape, dtype=torch.float64, device="cuda"))
+    h = p._h
+    ws = p.workspace(fwi.FWI_OP_FORWARD)
+    import ctypes
+    rc = p.lib.fwi_forward(h, ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
+                           ctypes.c_void_p(ws.data_ptr()), 16, None)
+    assert rc == fwi.FWI_OP_FORWARD - 3  # FWI_ENOMEM
