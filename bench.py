@@ -1,0 +1,250 @@
+#!/usr/bin/env python
+"""Throughput of the matrix-free Gauss-Newton Hessian-vector product on one
+MI355X.
+
+Workload (one "step"): on the seeded 921 x 301 layered-faulted model
+(dx = 10 m, 20 sponge cells per side), 64 surface shots, 461 receivers, Ricker
+8 Hz, 4000 time steps, forward checkpoints every 50 steps: one misfit gradient
+at the smoothed model plus one batched call of 16 Gauss-Newton Hessian-vector
+products on seeded smooth random vectors.  Inputs are resident in HBM before
+the timed region; the observed data are the forward data of the true model.
+
+Prints one JSON line: Hv/s (value), per-step time, Gpt-updates/s, the
+headline HBM fraction, the roofline of the dominant kernel (HIP-event times of
+every launch in the timed region), and the FP64 oracle timed on the host on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import re
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "GN Hessian-vector products/s + Gpt-updates/s (%HBM peak); p50/p99 Hv latency"
+KERNEL_NAMES = {0: "k_step<false>", 1: "k_step<true>", 2: "k_adjoint"}
+KERNEL_SRC = os.path.join(ROOT, "paper_2507_10804_amd", "csrc", "fwi_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_gn_hvp.md")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(g, B, nseg, K):
+    """Compulsory HBM bytes of one step (gradient + one B-vector Hv call),
+    per kernel kind: every array element a launch must read or write, once.
+
+    Np = padded grid points.  Per launch:
+      forward step      4 Np (3 ns + 1)       u^n, u^{n-1}, c -> u^{n+1}
+        + 4 ns nr         receiver gather (when data are recorded)
+        + 8 ns Np         checkpoint pair (every K-th step)
+        + 4 ns Np         w^n store (segment recompute)
+      forward+Born step 4 Np (3 ns + 1) + 4 Np B (3 ns + 1) + 4 B ns nr
+        + 8 ns Np         checkpoint pair (every K-th step)
+      adjoint step      12 Np B ns (mu^{k+1}, mu^{k+2} -> mu^k) + 4 B ns nr
+        + 4 Np ns + 8 Np + 16 Np B   w^k, c, 2/m and one FP64 image per
+                                     vector (steps with an image term)
+    """
+    nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
+    Np = nzp * nxp
+    ns, nr, nt = g.ns, g.nr, g.nt
+    ck_steps = nseg - 1
+    fwd = (nt - 1) * (4 * Np * (3 * ns + 1) + 4 * ns * nr) + ck_steps * 8 * ns * Np
+    rec = (nt - 1) * (4 * Np * (3 * ns + 1) + 4 * ns * Np)
+    born = ((nt - 1) * (4 * Np * (3 * ns + 1) + 4 * Np * B * (3 * ns + 1) + 4 * B * ns * nr)
+            + ck_steps * 8 * ns * Np)
+
+    def adj(b):
+        return nt * (12 * Np * b * ns + 4 * b * ns * nr) + (nt - 1) * (4 * Np * ns + 8 * Np + 16 * Np * b)
+
+    # gradient: forward (gathering d) + recompute + adjoint(B=1)
+    # Hv call : forward+Born + recompute + adjoint(B)
+    return {0: fwd + 2 * rec, 1: born, 2: adj(1) + adj(B)}
+
+
+def read_traffic(kind_name):
+    """HBM bytes per launch from committed rocprofv3 counter runs, or None if
+    absent or taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    m = re.search(r"kernel source sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    if not m or m.group(1) != kernel_source_hash():
+        return None
+    m = re.search(re.escape(kind_name) + r"\s*\|\s*([0-9.eE+]+)\s*\|", text)
+    return float(m.group(1)) if m else None
+
+
+def cpu_baseline(g, m, v, threads, nt_sample):
+    """The FP64 oracle, as it stands, on `threads` shots of the full grid for
+    nt_sample steps, one Gauss-Newton product; scaled to Hv/s of the whole
+    workload (64 shots x 4000 steps) by the fraction of shot-steps done."""
+    import oracle
+
+    oracle.build(force=False)
+    gs = g.with_shots(np.arange(threads)).with_nt(nt_sample)
+    t0 = time.perf_counter()
+    oracle.gn_hvp(gs, m, v, nthreads=threads)
+    dt = time.perf_counter() - t0
+    frac = (threads * (nt_sample - 1)) / (g.ns * (g.nt - 1))
+    return {"value": frac / dt, "unit": "Hv/s", "cores": threads, "kind": "oracle",
+            "sample": f"one GN Hv on {threads} of {g.ns} shots, full 921x301 grid, "
+                      f"{nt_sample} of {g.nt} steps, {dt:.1f} s wall; scaled by shot-steps"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--shots", type=int, default=64)
+    ap.add_argument("--nt", type=int, default=4000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-nt", type=int, default=300)
+    ap.add_argument("--no-profile", action="store_true",
+                    help="skip the per-launch HIP events (rocprofv3 runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
+              "with one all-reduce of the images, which this build does not run; "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2507_10804_amd import fwi, synth
+
+    g, m_true, m_eval = synth.config_layered(ns=args.shots, nt=args.nt)
+    B = args.batch
+    vs = synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, B + 1))
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    mt, me, vd = f32(m_true), f32(m_eval), f32(vs)
+    log(f"workload: 921x301 padded {plan.nzp}x{plan.nxp}, {g.ns} shots, {g.nr} receivers, "
+        f"nt={g.nt}, K={plan.K}, B={B}")
+    dobs = plan.forward(mt)  # synthetic observed data (untimed)
+    hv = torch.empty((B, g.nz, g.nx), dtype=torch.float32, device=dev)
+    torch.cuda.synchronize()
+    ws_gb = (plan.workspace_bytes(fwi.FWI_OP_GN_HVP, B) +
+             plan.workspace_bytes(fwi.FWI_OP_MISFIT_GRAD)) / 1e9
+
+    def step():
+        phi, grad = plan.misfit_grad(me, dobs)
+        plan.gn_hvp(me, vd, out=hv)
+        return phi, grad
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log(f"warmup step {i + 1}/{args.warmup} done")
+    if plan.status():
+        raise RuntimeError("device status flags set after warm-up")
+
+    if not args.no_profile:
+        plan.profile(True)
+        plan.profile_reset()
+    st = torch.cuda.current_stream(dev)
+    ev = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(st)
+        phi, grad = plan.misfit_grad(me, dobs)
+        e1.record(st)
+        plan.gn_hvp(me, vd, out=hv)
+        e2.record(st)
+        ev.append((e0, e1, e2))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for i in range(args.steps):
+        log(f"timed step {i + 1}/{args.steps}: {ev[i][0].elapsed_time(ev[i][2]):.1f} ms")
+    if plan.status():
+        raise RuntimeError("device status flags set in the timed region")
+
+    ms_step = wall * 1e3 / args.steps
+    hv_lat = np.array([e[1].elapsed_time(e[2]) for e in ev])
+    grad_lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
+    nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
+    solve_updates = g.ns * nzp * nxp * (g.nt - 1)
+    solves = 2 + 1 + 2 * B  # gradient: fwd + adj; Hv: fwd + B Born + B adjoint
+    gpts = solves * solve_updates / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": B / (ms_step * 1e-3),
+        "unit": "Hv/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"layered-faulted 921x301 dx=10m, {g.ns} shots, {g.nr} receivers, "
+                               f"Ricker 8 Hz, nt={g.nt}, K={plan.K}: misfit gradient + "
+                               f"{B} GN Hv per step",
+                   "grid": [g.nz, g.nx], "padded": [nzp, nxp], "shots": g.ns,
+                   "receivers": g.nr, "nt": g.nt, "batch": B, "ckpt_every": plan.K,
+                   "workspace_gb": round(ws_gb, 2)},
+        "gpt_updates_per_s": gpts,
+        "hbm_headline_frac": gpts * 1e9 * 16 / (HBM_PEAK_GBS * 1e9),
+        "hv_call_latency_ms": {"p50": float(np.percentile(hv_lat, 50)),
+                               "p99": float(np.percentile(hv_lat, 99)), "batch": B},
+        "grad_latency_ms": float(np.median(grad_lat)),
+    }
+
+    if not args.no_profile:
+        nseg = (g.nt - 1 + plan.K - 1) // plan.K
+        alg = algorithmic_bytes(g, B, nseg, plan.K)
+        kern = {}
+        for kind, name in KERNEL_NAMES.items():
+            ms, n = plan.profile_read(kind)
+            n_step = n / args.steps
+            per_launch = alg[kind] / n_step if n_step else 0.0
+            kern[name] = {"launches_per_step": n_step, "avg_us": 1e3 * ms / max(n, 1),
+                          "total_ms_per_step": ms / args.steps,
+                          "alg_bytes_per_launch": per_launch,
+                          "achieved_gbs": per_launch / (1e-3 * ms / max(n, 1)) / 1e9 if n else 0}
+        plan.profile(False)
+        dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"])
+        k = kern[dom]
+        traffic = read_traffic(dom)
+        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": k["achieved_gbs"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": k["achieved_gbs"] / HBM_PEAK_GBS,
+                           "traffic": traffic,
+                           "alg_bytes_per_launch": k["alg_bytes_per_launch"],
+                           "avg_launch_us": k["avg_us"]}
+        out["kernels"] = kern
+
+    if not args.no_cpu_baseline:
+        try:
+            threads = min(16, len(os.sched_getaffinity(0)))
+        except AttributeError:
+            threads = min(16, os.cpu_count() or 1)
+        out["cpu_baseline"] = cpu_baseline(g, m_eval, vs[0], threads, args.cpu_nt)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,21 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
 int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, void *ws,
                size_t ws_bytes, void *stream);
 
+/* Per-kernel timing telemetry.  While enabled, every launch of the three
+ * stencil kernels is bracketed by a pair of HIP events recorded on the
+ * call's stream (do not enable while the stream is being captured).
+ * fwi_profile_read synchronises on the recorded events and returns, for one
+ * kernel kind, the summed duration in milliseconds and the launch count since
+ * the last reset.  Kinds: */
+enum {
+  FWI_KERNEL_STEP = 0,       /* forward (or recompute) time step */
+  FWI_KERNEL_STEP_BORN = 1,  /* forward + B Born fields time step */
+  FWI_KERNEL_ADJOINT = 2     /* adjoint + imaging time step */
+};
+int fwi_profile_enable(fwi_plan *p, int enable);
+int fwi_profile_read(fwi_plan *p, int kind, double *total_ms, int64_t *launches);
+int fwi_profile_reset(fwi_plan *p);
+
 /* Synchronise `stream`, return the device status word in *status and clear
  * it. */
 int fwi_status(fwi_plan *p, void *stream, uint32_t *status);

@@ -1,7 +1,9 @@
 """Build the gfx950 shared library ``libfwi_mi355x.so`` next to the package.
 
 hipcc cross-compiles for gfx950 without a GPU present.  Packed FP32 vector
-instructions are disabled for every HIP translation unit.
+instructions are disabled for every HIP translation unit, and implicit FMA
+contraction is off: kernels state their FMAs explicitly so that every kernel
+evaluates the leapfrog update in the same order.
 """
 from __future__ import annotations
 
@@ -16,7 +18,7 @@ LIB = os.path.join(PKG, "libfwi_mi355x.so")
 SOURCES = ["fwi_kernels.hip", "fwi_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
-FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
+FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 

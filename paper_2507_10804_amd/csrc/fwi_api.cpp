@@ -62,6 +62,14 @@ struct fwi_plan {
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
+  // telemetry: event pairs per kernel kind, from a reusable pool
+  bool profiling = false;
+  std::vector<hipEvent_t> pool;
+  size_t pool_used = 0;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> marks[3];
+  ~fwi_plan() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -149,6 +157,33 @@ int check_call(const fwi_plan *p, int op, int B, const void *ws, size_t ws_bytes
 
 float src_amp(const fwi_plan *p, int n) { return p->wavelet[n] / (p->dx * p->dx); }
 
+hipError_t next_event(fwi_plan *p, hipEvent_t *e) {
+  if (p->pool_used == p->pool.size()) {
+    hipEvent_t ev;
+    hipError_t rc = hipEventCreate(&ev);
+    if (rc != hipSuccess) return rc;
+    p->pool.push_back(ev);
+  }
+  *e = p->pool[p->pool_used++];
+  return hipSuccess;
+}
+
+// Launch one stencil kernel, bracketed by events when profiling.
+template <class F>
+hipError_t timed(fwi_plan *p, int kind, hipStream_t st, F &&launch) {
+  if (!p->profiling) return launch();
+  hipEvent_t a, b;
+  hipError_t rc = next_event(p, &a);
+  if (rc == hipSuccess) rc = next_event(p, &b);
+  if (rc == hipSuccess) rc = hipEventRecord(a, st);
+  if (rc != hipSuccess) return rc;
+  rc = launch();
+  if (rc != hipSuccess) return rc;
+  rc = hipEventRecord(b, st);
+  if (rc == hipSuccess) p->marks[kind].emplace_back(a, b);
+  return rc;
+}
+
 // Forward sweep n = 0..nt-2 on the fields at ws+L.u (and Born fields).
 int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, float *d_out,
                   float *dd_out, bool store_ckpt, hipStream_t st) {
@@ -170,7 +205,8 @@ int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, floa
       const int j = (n + 1) / p->K;
       if (j < p->nseg) a.ck = ckpt + (size_t)j * 2 * g.ns * g.fs;
     }
-    HIP_TRY(launch_step(g, p->tabs, a, born, st));
+    HIP_TRY(timed(p, born ? FWI_KERNEL_STEP_BORN : FWI_KERNEL_STEP, st,
+                  [&] { return launch_step(g, p->tabs, a, born, st); }));
   }
   return FWI_OK;
 }
@@ -204,13 +240,13 @@ int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
       f.n = n;
       f.src_amp = src_amp(p, n);
       f.w_out = wseg + (size_t)(n - n0) * g.ns * g.fs;
-      HIP_TRY(launch_step(g, p->tabs, f, false, st));
+      HIP_TRY(timed(p, FWI_KERNEL_STEP, st, [&] { return launch_step(g, p->tabs, f, false, st); }));
     }
     const int ktop = (j == p->nseg - 1) ? g.nt - 1 : n1 - 1;
     for (int k = ktop; k >= n0; --k) {
       a.k = k;
       a.w = (k <= g.nt - 2) ? wseg + (size_t)(k - n0) * g.ns * g.fs : nullptr;
-      HIP_TRY(launch_adjoint(g, p->tabs, a, st));
+      HIP_TRY(timed(p, FWI_KERNEL_ADJOINT, st, [&] { return launch_adjoint(g, p->tabs, a, st); }));
     }
   }
   return FWI_OK;
@@ -504,6 +540,34 @@ int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, vo
   if (int rc = reverse_sweep(p, L, ws, B, dd, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, p->inv_noise_var, hv, st));
   HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_profile_enable(fwi_plan *p, int enable) {
+  if (!p) return fail(FWI_EINVAL, "null plan");
+  p->profiling = enable != 0;
+  return FWI_OK;
+}
+
+int fwi_profile_reset(fwi_plan *p) {
+  if (!p) return fail(FWI_EINVAL, "null plan");
+  for (auto &m : p->marks) m.clear();
+  p->pool_used = 0;
+  return FWI_OK;
+}
+
+int fwi_profile_read(fwi_plan *p, int kind, double *total_ms, int64_t *launches) {
+  if (!p || !total_ms || !launches) return fail(FWI_EINVAL, "null argument");
+  if (kind < 0 || kind > 2) return fail(FWI_EINVAL, "unknown kernel kind");
+  double acc = 0.0;
+  for (auto &pr : p->marks[kind]) {
+    HIP_TRY(hipEventSynchronize(pr.second));
+    float ms = 0.0f;
+    HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+    acc += ms;
+  }
+  *total_ms = acc;
+  *launches = (int64_t)p->marks[kind].size();
   return FWI_OK;
 }
 

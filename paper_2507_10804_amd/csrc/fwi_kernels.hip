@@ -38,35 +38,64 @@ __device__ __forceinline__ float sponge_kappa(const Geo &g, int i, int j) {
   return g.kmax * (fx * fx + fz * fz);
 }
 
-// 2a and b of the damped leapfrog at padded cell (i, j).
+// 2a and b of the damped leapfrog at padded cell (i, j).  The hardware
+// reciprocal is exact at kappa = 0 (the whole interior); every kernel uses
+// this one function, so forward and adjoint see identical coefficients.
 __device__ __forceinline__ void sponge_ab(const Geo &g, int i, int j, float &a2, float &b) {
   const float kap = sponge_kappa(g, i, j);
-  const float inv = 1.0f / (1.0f + kap);
+  const float inv = __builtin_amdgcn_rcpf(1.0f + kap);
   a2 = 2.0f * inv;
   b = (1.0f - kap) * inv;
 }
 
-// Stage tile (i0, j0) of field f, with a HALO-wide border, into LDS.  Values
-// outside the padded grid are the zero boundary of the scheme.
-__device__ __forceinline__ void load_tile(float *__restrict__ L, const float *__restrict__ f,
-                                          int i0, int j0, const Geo &g, int tid) {
+// One damped leapfrog update, a2 u - b u_prev + c w, in a fixed evaluation
+// order.  The library is built without implicit FMA contraction, so every
+// kernel that advances a wavefield (forward, forward+Born, segment recompute,
+// adjoint) rounds identically and recomputed wavefields match the stored
+// ones bit for bit.
+__device__ __forceinline__ float leapfrog(float a2, float b, float u, float um, float c, float w) {
+  return __builtin_fmaf(c, w, __builtin_fmaf(a2, u, -(b * um)));
+}
+
+// A tile (i0, j0) of one field with a HALO-wide border, as fetched by one
+// thread before it is committed to LDS.  Values outside the padded grid are
+// the zero boundary of the scheme.  Every load is issued unconditionally from
+// a clamped (in-grid) address and masked afterwards, so all of a thread's
+// loads are in flight together; fetch and commit are split so that other
+// loads can join the same round trip.
+struct TileRegs {
+  float v[LH / NWAVE];
+  float h;
+};
+
+__device__ __forceinline__ void fetch_tile(TileRegs &T, const float *__restrict__ f, int i0,
+                                           int j0, const Geo &g, int tid) {
   const int lane = tid % TX, wv = tid / TX;
   const int j = j0 + lane;
+  const int jc = min(j, g.nxp - 1);
   const bool jok = j < g.nxp;
 #pragma unroll
   for (int q = 0; q < LH / NWAVE; ++q) {
-    const int r = wv + q * NWAVE;
-    const int i = i0 - HALO + r;
-    float v = 0.0f;
-    if (jok && i >= 0 && i < g.nzp) v = f[(long long)i * g.pitch + j];
-    L[r * LW + HALO + lane] = v;
+    const int i = i0 - HALO + wv + q * NWAVE;
+    const int ic = min(max(i, 0), g.nzp - 1);
+    // multiply by a 0/1 mask instead of selecting: the load stays
+    // unconditional (a select lets the compiler sink it into a branch)
+    T.v[q] = f[ic * g.pitch + jc] * ((jok && i >= 0 && i < g.nzp) ? 1.0f : 0.0f);
   }
   const int r = tid / (2 * HALO), c = tid % (2 * HALO);
   const int col = c < HALO ? c - HALO : TX + c - HALO;
   const int i = i0 + r, jj = j0 + col;
-  float v = 0.0f;
-  if (i < g.nzp && jj >= 0 && jj < g.nxp) v = f[(long long)i * g.pitch + jj];
-  L[(r + HALO) * LW + HALO + col] = v;
+  T.h = f[min(i, g.nzp - 1) * g.pitch + min(max(jj, 0), g.nxp - 1)] *
+        ((i < g.nzp && jj >= 0 && jj < g.nxp) ? 1.0f : 0.0f);
+}
+
+__device__ __forceinline__ void commit_tile(float *__restrict__ L, const TileRegs &T, int tid) {
+  const int lane = tid % TX, wv = tid / TX;
+#pragma unroll
+  for (int q = 0; q < LH / NWAVE; ++q) L[(wv + q * NWAVE) * LW + HALO + lane] = T.v[q];
+  const int r = tid / (2 * HALO), c = tid % (2 * HALO);
+  const int col = c < HALO ? c - HALO : TX + c - HALO;
+  L[(r + HALO) * LW + HALO + col] = T.h;
 }
 
 // L applied at the RZ rows this thread owns; ctr receives the centre values.
@@ -90,7 +119,7 @@ __device__ __forceinline__ void laplacian_rows(const float *__restrict__ L, cons
       const float sk = ((col[r + 4 - k] - u) + (col[r + 4 + k] - u)) +
                        ((row[-k] - u) + (row[k] - u));
       const float ck = k == 1 ? g.c1 : k == 2 ? g.c2 : k == 3 ? g.c3 : g.c4;
-      acc += ck * sk;
+      acc = __builtin_fmaf(ck, sk, acc);
     }
     lap[r] = acc;
     ctr[r] = u;
@@ -127,7 +156,21 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
   const float *un = ubase + (a.n & 1) * fs;
   float *uo = ubase + ((a.n + 1) & 1) * fs;
 
-  load_tile(L, un, i0, j0, g, tid);
+  // element (ib + r, j) of every per-point array sits at idx[r]; rows and
+  // columns outside the grid read a clamped element and store nothing
+  const int jc = min(j, g.nxp - 1);
+  const bool jok = j < g.nxp;
+  int idx[RZ];
+  float cc[RZ], unew[RZ], um[RZ];
+  TileRegs T;
+  fetch_tile(T, un, i0, j0, g, tid);
+#pragma unroll
+  for (int r = 0; r < RZ; ++r) {
+    idx[r] = min(ib + r, g.nzp - 1) * g.pitch + jc;
+    cc[r] = a.c[idx[r]];
+    um[r] = uo[idx[r]];
+  }
+  commit_tile(L, T, tid);
   __syncthreads();
   float w[RZ], ctr[RZ];
   laplacian_rows(L, g, lane, wv, w, ctr);
@@ -140,25 +183,20 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
     }
   }
 
-  // element (ib + r, j) of every per-point array sits at idx0 + r * pitch
-  const int idx0 = ib * g.pitch + j;
-  const bool jok = j < g.nxp;
-  float cc[RZ], unew[RZ];
+  // rows outside the grid compute on clamped copies and store nothing
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    const int i = ib + r, idx = idx0 + r * g.pitch;
-    cc[r] = unew[r] = 0.0f;
-    if (jok && i < g.nzp) {
-      float a2, bb;
-      cc[r] = a.c[idx];
-      sponge_ab(g, i, j, a2, bb);
-      const float um = uo[idx];
-      unew[r] = a2 * ctr[r] - bb * um + cc[r] * w[r];
-      uo[idx] = unew[r];
-      if (a.w_out) a.w_out[s * fs + idx] = w[r];
+    const int i = ib + r;
+    const bool ok = jok && i < g.nzp;
+    float a2, bb;
+    sponge_ab(g, i, j, a2, bb);
+    unew[r] = leapfrog(a2, bb, ctr[r], um[r], cc[r], w[r]);
+    if (ok) {
+      uo[idx[r]] = unew[r];
+      if (a.w_out) a.w_out[s * fs + idx[r]] = w[r];
       if (a.ck) {
-        a.ck[(2 * s + ((a.n + 1) & 1)) * fs + idx] = unew[r];
-        a.ck[(2 * s + (a.n & 1)) * fs + idx] = ctr[r];
+        a.ck[(2 * s + ((a.n + 1) & 1)) * fs + idx[r]] = unew[r];
+        a.ck[(2 * s + (a.n & 1)) * fs + idx[r]] = ctr[r];
       }
     }
   }
@@ -174,22 +212,26 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
       const float *dn = dbase + (a.n & 1) * fs;
       float *dout = dbase + ((a.n + 1) & 1) * fs;
       const float *dcb = a.dc + (long long)b * fs;
+      float lap[RZ], dctr[RZ], dnew[RZ], dm[RZ], dcv[RZ];
+      TileRegs D;
+      fetch_tile(D, dn, i0, j0, g, tid);
+#pragma unroll
+      for (int r = 0; r < RZ; ++r) {
+        dm[r] = dout[idx[r]];
+        dcv[r] = dcb[idx[r]];
+      }
       __syncthreads();
-      load_tile(L, dn, i0, j0, g, tid);
+      commit_tile(L, D, tid);
       __syncthreads();
-      float lap[RZ], dctr[RZ], dnew[RZ];
       laplacian_rows(L, g, lane, wv, lap, dctr);
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
-        const int i = ib + r, idx = idx0 + r * g.pitch;
-        dnew[r] = 0.0f;
-        if (jok && i < g.nzp) {
-          float a2, bb;
-          sponge_ab(g, i, j, a2, bb);
-          const float dm = dout[idx];
-          dnew[r] = a2 * dctr[r] - bb * dm + cc[r] * lap[r] + dcb[idx] * w[r];
-          dout[idx] = dnew[r];
-        }
+        const int i = ib + r;
+        const bool ok = jok && i < g.nzp;
+        float a2, bb;
+        sponge_ab(g, i, j, a2, bb);
+        dnew[r] = __builtin_fmaf(dcv[r], w[r], leapfrog(a2, bb, dctr[r], dm[r], cc[r], lap[r]));
+        if (ok) dout[idx[r]] = dnew[r];
       }
       if (a.dd_out && rp1 > rp0)
         gather_receivers(L, dnew, t, rp0, rp1, tid,
@@ -214,13 +256,15 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
   const int j = j0 + lane, ib = i0 + wv * RZ;
   const long long fs = g.fs;
 
-  const int idx0 = ib * g.pitch + j;
+  const int jc = min(j, g.nxp - 1);
   const bool jok = j < g.nxp;
   float cc[RZ], img[RZ];
+  int idx[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    cc[r] = img[r] = 0.0f;
-    if (jok && ib + r < g.nzp) cc[r] = a.c[idx0 + r * g.pitch];
+    idx[r] = min(ib + r, g.nzp - 1) * g.pitch + jc;
+    cc[r] = a.c[idx[r]];
+    img[r] = 0.0f;
   }
   const int np0 = t.tile_node_ptr[tile], np1 = t.tile_node_ptr[tile + 1];
   const bool inject = (a.r != nullptr) && (np1 > np0);
@@ -230,22 +274,25 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
     float *mb = a.mu + ((long long)b * g.ns + s) * 2 * fs;
     const float *m1 = mb + ((a.k + 1) & 1) * fs;
     float *m0 = mb + (a.k & 1) * fs;
-    if (s > s0) __syncthreads();
-    load_tile(L, m1, i0, j0, g, tid);
-    __syncthreads();
-    float lap[RZ], ctr[RZ], out[RZ];
-    laplacian_rows(L, g, lane, wv, lap, ctr);
+    float lap[RZ], ctr[RZ], out[RZ], m2[RZ], wv_[RZ];
     const float *ws_ = a.w ? a.w + s * fs : nullptr;
+    TileRegs T;
+    fetch_tile(T, m1, i0, j0, g, tid);
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
-      const int i = ib + r, idx = idx0 + r * g.pitch;
-      out[r] = 0.0f;
-      if (jok && i < g.nzp) {
-        float a2, bb;
-        sponge_ab(g, i, j, a2, bb);
-        out[r] = a2 * ctr[r] - bb * m0[idx] + cc[r] * lap[r];
-        if (ws_) img[r] += ws_[idx] * ctr[r];
-      }
+      m2[r] = m0[idx[r]];
+      wv_[r] = ws_ ? ws_[idx[r]] : 0.0f;
+    }
+    if (s > s0) __syncthreads();
+    commit_tile(L, T, tid);
+    __syncthreads();
+    laplacian_rows(L, g, lane, wv, lap, ctr);
+#pragma unroll
+    for (int r = 0; r < RZ; ++r) {
+      float a2, bb;
+      sponge_ab(g, ib + r, j, a2, bb);
+      out[r] = leapfrog(a2, bb, ctr[r], m2[r], cc[r], lap[r]);
+      img[r] = __builtin_fmaf(wv_[r], ctr[r], img[r]);
     }
     if (inject) {
       __syncthreads();
@@ -264,15 +311,20 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
     }
 #pragma unroll
     for (int r = 0; r < RZ; ++r)
-      if (jok && ib + r < g.nzp) m0[idx0 + r * g.pitch] = out[r];
+      if (jok && ib + r < g.nzp) m0[idx[r]] = out[r];
   }
   if (a.w) {
     double *ig = a.img + ((long long)grp * a.B + b) * fs;
+    double old[RZ];
+    float sm[RZ];
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
-      const int idx = idx0 + r * g.pitch;
-      if (jok && ib + r < g.nzp) ig[idx] += (double)a.s2m[idx] * (double)img[r];
+      old[r] = ig[idx[r]];
+      sm[r] = a.s2m[idx[r]];
     }
+#pragma unroll
+    for (int r = 0; r < RZ; ++r)
+      if (jok && ib + r < g.nzp) ig[idx[r]] = old[r] + (double)sm[r] * (double)img[r];
   }
 }
 

@@ -22,7 +22,8 @@ STATUS_BAD_MODEL, STATUS_CFL, STATUS_NONFINITE = 1, 2, 4
 EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_device_bytes",
            "fwi_plan_bind", "fwi_workspace_size", "fwi_plan_dims", "fwi_forward", "fwi_born",
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
-           "fwi_last_error"]
+           "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset"]
+KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
 class FwiError(RuntimeError):
@@ -70,6 +71,9 @@ def load_library(path: str = LIB_PATH):
             "fwi_status": ([P, P, P], I),
             "fwi_strerror": ([I], ctypes.c_char_p),
             "fwi_last_error": ([], ctypes.c_char_p),
+            "fwi_profile_enable": ([P, I], I),
+            "fwi_profile_read": ([P, I, P, P], I),
+            "fwi_profile_reset": ([P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -228,6 +232,20 @@ class Plan:
         _check(self.lib.fwi_gn_hvp(self._h, self._p(m), self._p(v), B, self._p(hv),
                                    self._p(ws), ws.numel(), self._stream()))
         return hv[0] if single else hv
+
+    def profile(self, enable=True):
+        """Bracket every stencil-kernel launch with HIP events (telemetry)."""
+        _check(self.lib.fwi_profile_enable(self._h, int(bool(enable))))
+
+    def profile_reset(self):
+        _check(self.lib.fwi_profile_reset(self._h))
+
+    def profile_read(self, kind):
+        """(total milliseconds, launches) of one kernel kind since the reset."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        _check(self.lib.fwi_profile_read(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
 
     def status(self):
         """Synchronise, return and clear the device status bits."""

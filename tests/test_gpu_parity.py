@@ -90,7 +90,25 @@ def test_small_misfit_grad(torch, small):
     # the residual d - dobs is a difference of close data sets, so the data
     # tolerance is amplified by |d| / |d - dobs| in Phi
     amp = np.linalg.norm(dobs) / np.linalg.norm(oracle.forward(g, m) - dobs)
+    say(f"  residual amplification |d|/|d - dobs| = {amp:.0f}")
     assert float(phi) == pytest.approx(phi_o, rel=2 * TOL_DATA * amp)
+    # the gradient is J^T of that residual: same amplification of the data error
+    assert rel(host(grad), grad_o) < max(TOL_IMAGE, 3 * TOL_DATA * amp)
+
+
+def test_misfit_grad_well_conditioned(torch, small):
+    """Gradient at a model 5% faster than the truth: the direct arrivals move,
+    the residual is comparable to the data (|d|/|r| small) and the FP32
+    gradient meets the image tolerance."""
+    say("entry: fwi_misfit_grad small, 5% faster model")
+    g, dobs = small["g"], small["dobs"]
+    m0 = 1.05 * small["m_true"]
+    phi, grad = small["plan"].misfit_grad(dev(torch, m0), dev(torch, dobs))
+    phi_o, grad_o = oracle.misfit_grad(g, m0, dobs)
+    amp = np.linalg.norm(dobs) / np.sqrt(2 * phi_o)
+    say(f"  residual amplification {amp:.1f}")
+    assert amp < 20
+    assert float(phi) == pytest.approx(phi_o, rel=1e-4)
     assert rel(host(grad), grad_o) < TOL_IMAGE
 
 
