@@ -108,6 +108,27 @@ def cpu_baseline(g, m, v, threads, nt_sample):
                       f"{nt_sample} of {g.nt} steps, {dt:.1f} s wall; scaled by shot-steps"}
 
 
+def calibrate_copy(nbytes=2 << 30, reps=5):
+    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
+    the scale from counter units to bytes, its time the attainable HBM rate."""
+    import torch
+
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                      "avg_ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -120,7 +141,13 @@ def main():
     ap.add_argument("--cpu-nt", type=int, default=300)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-launch HIP events (rocprofv3 runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only time a plain device-to-device copy of 2 GiB (the "
+                         "reference kernel for HBM counters and attainable bandwidth)")
     args = ap.parse_args()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
               "with one all-reduce of the images, which this build does not run; "

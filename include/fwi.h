@@ -83,7 +83,8 @@ enum {
   FWI_OP_BORN = 1,
   FWI_OP_ADJOINT = 2,
   FWI_OP_MISFIT_GRAD = 3,
-  FWI_OP_GN_HVP = 4
+  FWI_OP_GN_HVP = 4,
+  FWI_OP_MISFIT = 5
 };
 
 typedef struct fwi_plan fwi_plan;
@@ -142,6 +143,26 @@ int fwi_born(fwi_plan *p, const float *m, const float *v, int B, float *dd, void
  * data vectors r[B][ns][nt][nr] (no noise weighting). */
 int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *g, void *ws,
                 size_t ws_bytes, void *stream);
+
+/* Forward map that also leaves in `ws` the coefficients and forward
+ * checkpoints (every K steps) that fwi_adjoint_resume needs: d as
+ * fwi_forward.  `ws` must be sized for FWI_OP_ADJOINT with the largest batch
+ * the later adjoint calls will use. */
+int fwi_forward_keep(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_bytes,
+                     void *stream);
+
+/* Migration g[B][nz][nx] = sum_s J_s^T r_{b,s} (as fwi_adjoint) at the model
+ * of the last fwi_forward_keep on this workspace, recomputing the forward
+ * wavefield segment by segment from its checkpoints instead of solving the
+ * forward again.  May be repeated; the checkpoints are left intact. */
+int fwi_adjoint_resume(fwi_plan *p, const float *r, int B, float *g, void *ws,
+                       size_t ws_bytes, void *stream);
+
+/* Data misfit only (the quantity an MCMC proposal is accepted on, Section
+ * 2.3): *phi (device double) = 1/2 inv_noise_var sum |d(m) - dobs|^2.  One
+ * forward solve, no checkpoints. */
+int fwi_misfit(fwi_plan *p, const float *m, const float *dobs, double *phi, void *ws,
+               size_t ws_bytes, void *stream);
 
 /* Data misfit and its gradient (Section 2.1, eq. grad, misfit half):
  * *phi (device double) = 1/2 inv_noise_var sum |d(m) - dobs|^2,

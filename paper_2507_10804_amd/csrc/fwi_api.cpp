@@ -22,6 +22,7 @@ hipError_t launch_setup(const Geo &g, const float *m, const float *v, int B, flo
                         float *s2m, float *dc, unsigned int *status, hipStream_t st);
 hipError_t launch_fill(float *p, long long n, hipStream_t st);
 hipError_t launch_fill64(double *p, long long n, hipStream_t st);
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st);
 hipError_t launch_zero_t0(float *d, int count, int nt, int nr, hipStream_t st);
 hipError_t launch_residual(float *d, const float *dobs, long long n, double *part, int nparts,
                            double scale, double *phi, hipStream_t st);
@@ -62,6 +63,7 @@ struct fwi_plan {
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
+  int step_order = 0, born_order = 0, adj_order = 0;  // workgroup orders
   // telemetry: event pairs per kernel kind, from a reusable pool
   bool profiling = false;
   std::vector<hipEvent_t> pool;
@@ -113,7 +115,7 @@ Layout layout(const fwi_plan *p, int op, int B) {
   L.u = take(F * 2 * g.ns);
   if (needs_dc) L.du = take(F * 2 * g.ns * B);
   if (op == FWI_OP_GN_HVP) L.dd = take(ndata * B);
-  if (op == FWI_OP_MISFIT_GRAD) {
+  if (op == FWI_OP_MISFIT_GRAD || op == FWI_OP_MISFIT) {
     L.dres = take(ndata);
     L.part = take(NPARTS * sizeof(double));
   }
@@ -196,6 +198,7 @@ int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, floa
   a.B = born ? B : 0;
   a.d_out = d_out;
   a.dd_out = dd_out;
+  a.order = born ? p->born_order : p->step_order;
   float *ckpt = store_ckpt ? at<float>(ws, L.ckpt) : nullptr;
   for (int n = 0; n + 1 < g.nt; ++n) {
     a.n = n;
@@ -230,12 +233,17 @@ int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
   a.B = B;
   a.group = L.group;
   a.ngroups = L.G;
+  a.order = p->adj_order;
+  f.order = p->step_order;
   float *ckpt = at<float>(ws, L.ckpt);
   float *wseg = at<float>(ws, L.wseg);
   for (int j = p->nseg - 1; j >= 0; --j) {
     const int n0 = j * p->K;
     const int n1 = std::min((j + 1) * p->K, g.nt - 1);
-    f.u = ckpt + (size_t)j * 2 * g.ns * g.fs;  // recomputed in place: used once
+    // recompute on a copy so the checkpoints survive (the adjoint can be
+    // repeated after one forward, see fwi_adjoint_resume)
+    f.u = at<float>(ws, L.u);
+    HIP_TRY(launch_copy(f.u, ckpt + (size_t)j * 2 * g.ns * g.fs, (long long)2 * g.ns * g.fs, st));
     for (int n = n0; n < n1; ++n) {
       f.n = n;
       f.src_amp = src_amp(p, n);
@@ -347,7 +355,11 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   p->nseg = (G.nt - 1 + p->K - 1) / p->K;
   p->inv_noise_var = G.inv_noise_var;
   p->wavelet.assign(G.wavelet, G.wavelet + G.nt);
+  // tuning knobs for experiments; the defaults are the measured best
   if (const char *e = std::getenv("FWI_ADJ_GROUP")) p->adj_group_override = std::atoi(e);
+  if (const char *e = std::getenv("FWI_STEP_ORDER")) p->step_order = std::atoi(e) != 0;
+  if (const char *e = std::getenv("FWI_BORN_ORDER")) p->born_order = std::atoi(e) != 0;
+  if (const char *e = std::getenv("FWI_ADJ_ORDER")) p->adj_order = std::atoi(e) != 0;
 
   // receiver tables: sort receivers by (tile, local index, number)
   std::vector<std::tuple<int, int, int, long long>> recs;  // tile, local, id, gidx
@@ -458,7 +470,7 @@ int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream) {
 
 int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes) {
   if (!p || !bytes) return fail(FWI_EINVAL, "null argument");
-  if (op < FWI_OP_FORWARD || op > FWI_OP_GN_HVP) return fail(FWI_EINVAL, "unknown op");
+  if (op < FWI_OP_FORWARD || op > FWI_OP_MISFIT) return fail(FWI_EINVAL, "unknown op");
   if (batch < 1 || batch > 4096) return fail(FWI_EINVAL, "batch must be in [1, 4096]");
   *bytes = layout(p, op, batch).total;
   return FWI_OK;
@@ -504,6 +516,49 @@ int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *gout,
   if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 1.0, gout, st));
   HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_forward_keep(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_bytes,
+                     void *stream) {
+  if (int rc = check_call(p, FWI_OP_ADJOINT, 1, ws, ws_bytes)) return rc;
+  if (!m || !d) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_ADJOINT, 1);
+  const Geo &g = p->geo;
+  if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
+  HIP_TRY(launch_zero_t0(d, g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, 1, false, d, nullptr, true, st)) return rc;
+  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_adjoint_resume(fwi_plan *p, const float *r, int B, float *gout, void *ws,
+                       size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_ADJOINT, B, ws, ws_bytes)) return rc;
+  if (!r || !gout) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_ADJOINT, B);
+  const Geo &g = p->geo;
+  if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 1.0, gout, st));
+  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_misfit(fwi_plan *p, const float *m, const float *dobs, double *phi, void *ws,
+               size_t ws_bytes, void *stream) {
+  if (int rc = check_call(p, FWI_OP_MISFIT, 1, ws, ws_bytes)) return rc;
+  if (!m || !dobs || !phi) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_MISFIT, 1);
+  const Geo &g = p->geo;
+  float *dres = at<float>(ws, L.dres);
+  if (int rc = prologue(p, L, ws, m, nullptr, 0, false, false, st)) return rc;
+  HIP_TRY(launch_zero_t0(dres, g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, 1, false, dres, nullptr, false, st)) return rc;
+  HIP_TRY(launch_residual(dres, dobs, (long long)g.ns * g.nt * g.nr, at<double>(ws, L.part),
+                          NPARTS, 0.5 * p->inv_noise_var, phi, st));
   return FWI_OK;
 }
 

@@ -64,6 +64,7 @@ struct StepArgs {
   int n;              // step: computes u^{n+1}
   int B;
   float src_amp;      // s(n dt) / dx^2
+  int order;          // workgroup order: 0 shot-major, 1 tile-major
 };
 
 // Arguments of one adjoint + imaging time step (mu = c * lambda form).
@@ -78,6 +79,7 @@ struct AdjArgs {
   int B;
   int group;          // shots per workgroup
   int ngroups;
+  int order;          // workgroup order: 0 vector-major, 1 tile-major
 };
 
 }  // namespace fwi

@@ -145,7 +145,11 @@ template <bool BORN>
 __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs a) {
   __shared__ float L[LH * LW];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
-  const int s = lid / g.ntiles, tile = lid - s * g.ntiles;
+  // order 0: shot-major (neighbouring tiles of one shot are adjacent ids);
+  // order 1: tile-major (the shots of one tile are adjacent ids, so operands
+  // shared by all shots, such as the Born coefficients, are reused from L2)
+  const int s = a.order ? lid % g.ns : lid / g.ntiles;
+  const int tile = a.order ? lid / g.ns : lid - s * g.ntiles;
   const int tzi = tile / g.tiles_x, txi = tile - tzi * g.tiles_x;
   const int i0 = tzi * TZ, j0 = txi * TX;
   const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
@@ -247,9 +251,20 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
 __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArgs a) {
   __shared__ float L[LH * LW];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tile = lid % g.ntiles;
-  const int rest = lid / g.ntiles;
-  const int b = rest % a.B, grp = rest / a.B;
+  // order 0: field-major, tile fastest; order 1: tile-major with the vector
+  // index fastest, so the forward wavefield w of a shot group (shared by all
+  // vectors) is reused from L2 by consecutive workgroups
+  int tile, b, grp;
+  if (a.order) {
+    b = lid % a.B;
+    grp = (lid / a.B) % a.ngroups;
+    tile = lid / (a.B * a.ngroups);
+  } else {
+    tile = lid % g.ntiles;
+    const int rest = lid / g.ntiles;
+    b = rest % a.B;
+    grp = rest / a.B;
+  }
   const int tzi = tile / g.tiles_x, txi = tile - tzi * g.tiles_x;
   const int i0 = tzi * TZ, j0 = txi * TX;
   const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
@@ -361,6 +376,12 @@ __global__ void k_setup(Geo g, const float *__restrict__ m, const float *__restr
 __global__ void k_fill(float *__restrict__ p, long long n, float val) {
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride) p[q] = val;
+}
+
+__global__ void k_copy(float *__restrict__ dst, const float *__restrict__ src, long long n) {
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < n; q += stride)
+    dst[q] = src[q];
 }
 
 __global__ void k_fill64(double *__restrict__ p, long long n) {
@@ -476,6 +497,12 @@ hipError_t launch_setup(const Geo &g, const float *m, const float *v, int B, flo
 hipError_t launch_fill(float *p, long long n, hipStream_t st) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 1024)), dim3(256), 0, st, p, n, 0.0f);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy, dim3(blocks_for(n, 1024)), dim3(256), 0, st, dst, src, n);
   return hipGetLastError();
 }
 

@@ -16,13 +16,14 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfwi_mi355x.so")
 
-FWI_OP_FORWARD, FWI_OP_BORN, FWI_OP_ADJOINT, FWI_OP_MISFIT_GRAD, FWI_OP_GN_HVP = range(5)
+FWI_OP_FORWARD, FWI_OP_BORN, FWI_OP_ADJOINT, FWI_OP_MISFIT_GRAD, FWI_OP_GN_HVP, FWI_OP_MISFIT = range(6)
 STATUS_BAD_MODEL, STATUS_CFL, STATUS_NONFINITE = 1, 2, 4
 
 EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_device_bytes",
            "fwi_plan_bind", "fwi_workspace_size", "fwi_plan_dims", "fwi_forward", "fwi_born",
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
-           "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset"]
+           "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset",
+           "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -74,6 +75,9 @@ def load_library(path: str = LIB_PATH):
             "fwi_profile_enable": ([P, I], I),
             "fwi_profile_read": ([P, I, P, P], I),
             "fwi_profile_reset": ([P], I),
+            "fwi_forward_keep": ([P, P, P, P, Z, P], I),
+            "fwi_adjoint_resume": ([P, P, I, P, P, Z, P], I),
+            "fwi_misfit": ([P, P, P, P, P, Z, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -205,6 +209,45 @@ class Plan:
         _check(self.lib.fwi_adjoint(self._h, self._p(m), self._p(r), B, self._p(out),
                                     self._p(ws), ws.numel(), self._stream()))
         return out[0] if single else out
+
+    def forward_keep(self, m, ws):
+        """Forward data, leaving coefficients and checkpoints in `ws` (a
+        workspace tensor of workspace_bytes(FWI_OP_ADJOINT, batch) bytes)."""
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        d = self.torch.empty((g.ns, g.nt, g.nr), dtype=self.torch.float32, device=self.device)
+        _check(self.lib.fwi_forward_keep(self._h, self._p(m), self._p(d), self._p(ws),
+                                         ws.numel(), self._stream()))
+        return d
+
+    def adjoint_resume(self, r, ws):
+        """J^T r at the model of the last forward_keep on `ws`."""
+        g = self.geom
+        r = self._in(r, (g.ns, g.nt, g.nr), "r")
+        single = r.dim() == 3
+        r = r.reshape(-1, g.ns, g.nt, g.nr)
+        B = r.shape[0]
+        out = self.torch.empty((B, g.nz, g.nx), dtype=self.torch.float32, device=self.device)
+        _check(self.lib.fwi_adjoint_resume(self._h, self._p(r), B, self._p(out), self._p(ws),
+                                           ws.numel(), self._stream()))
+        return out[0] if single else out
+
+    def new_workspace(self, op, batch=1):
+        """A workspace owned by the caller (not cached by the plan)."""
+        return self.torch.empty(self.workspace_bytes(op, batch), dtype=self.torch.uint8,
+                                device=self.device)
+
+    def misfit(self, m, dobs, out=None):
+        """Phi = 1/2 inv_noise_var |f(m) - dobs|^2 as a device FP64 scalar."""
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        dobs = self._in(dobs, (g.ns, g.nt, g.nr), "dobs")
+        phi = out if out is not None else self.torch.empty((), dtype=self.torch.float64,
+                                                           device=self.device)
+        ws = self.workspace(FWI_OP_MISFIT)
+        _check(self.lib.fwi_misfit(self._h, self._p(m), self._p(dobs), self._p(phi),
+                                   self._p(ws), ws.numel(), self._stream()))
+        return phi
 
     def misfit_grad(self, m, dobs):
         g = self.geom

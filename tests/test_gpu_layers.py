@@ -1,0 +1,136 @@
+"""GPU tests of the layers above the C ABI: the autograd Function (checked
+against the FP64 oracle and central finite differences), the fused misfit,
+the checkpoint-resuming adjoint and the graph-captured probing session."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2507_10804_amd import synth
+from tests._cases import rel, tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def dev(torch, x):
+    return torch.as_tensor(np.asarray(x, dtype=np.float32), device="cuda")
+
+
+def host(x):
+    return x.detach().double().cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def case(torch):
+    from paper_2507_10804_amd import fwi
+    g, m_true, _ = synth.config_small()
+    m = 1.05 * m_true  # residual comparable to the data: well conditioned
+    dobs = oracle.forward(g, m_true)
+    v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
+    return dict(g=g, m=m, dobs=dobs, v=v, plan=fwi.Plan(g))
+
+
+def test_autograd_gradient_vs_oracle(torch, case):
+    from paper_2507_10804_amd import autograd as ag
+    say("entry: FwiForward backward (adjoint_resume) small")
+    g, plan = case["g"], case["plan"]
+    m = dev(torch, case["m"]).requires_grad_(True)
+    dobs = dev(torch, case["dobs"])
+    d = ag.forward(m, plan)
+    phi = 0.5 * ((d.double() - dobs.double()) ** 2).sum()
+    phi.backward()
+    phi_o, grad_o = oracle.misfit_grad(g, case["m"], case["dobs"])
+    assert float(phi) == pytest.approx(phi_o, rel=1e-4)
+    assert rel(host(m.grad), grad_o) < 1e-4
+    # the fused misfit Function gives the same gradient
+    m2 = dev(torch, case["m"]).requires_grad_(True)
+    ag.misfit(m2, dobs, plan).backward()
+    assert rel(host(m2.grad), grad_o) < 1e-4
+
+
+def test_backward_repeatable(torch, case):
+    from paper_2507_10804_amd import autograd as ag
+    say("entry: repeated backward on one forward")
+    plan = case["plan"]
+    m = dev(torch, case["m"]).requires_grad_(True)
+    d = ag.forward(m, plan)
+    r = dev(torch, synth.residual_noise(tuple(d.shape), seed=4))
+    (g1,) = torch.autograd.grad(d, m, grad_outputs=r, retain_graph=True)
+    (g2,) = torch.autograd.grad(d, m, grad_outputs=r)
+    assert torch.equal(g1, g2)
+    assert rel(host(g1), host(plan.adjoint(m.detach(), r))) < 1e-6
+
+
+def test_autograd_finite_difference(torch, case):
+    """Central difference of Phi along v, h = 1e-3 relative, against
+    <grad, v>: FP32 data limit the agreement to ~1e-3."""
+    from paper_2507_10804_amd import autograd as ag
+    say("entry: misfit finite difference small")
+    plan, v = case["plan"], case["v"]
+    m0 = case["m"]
+    dobs = dev(torch, case["dobs"])
+    m = dev(torch, m0).requires_grad_(True)
+    ag.misfit(m, dobs, plan).backward()
+    dirv = float(np.vdot(host(m.grad), v))
+    h = 1e-3 * np.abs(m0).max() / np.abs(v).max()
+    fp = float(plan.misfit(dev(torch, m0 + h * v), dobs))
+    fm = float(plan.misfit(dev(torch, m0 - h * v), dobs))
+    fd = (fp - fm) / (2 * h)
+    say(f"  FD {fd:.6e} vs <grad, v> {dirv:.6e}")
+    assert fd == pytest.approx(dirv, rel=2e-3)
+
+
+def test_jvp_and_gn_hvp_autograd(torch, case):
+    from paper_2507_10804_amd import autograd as ag
+    say("entry: forward-mode jvp and vjp-of-jvp small")
+    g, plan, m, v = case["g"], case["plan"], case["m"], case["v"]
+    jv = ag.born_jvp(dev(torch, m), dev(torch, v), plan)
+    assert rel(host(jv), oracle.born(g, m, v)) < 1e-5
+    hv = ag.gn_hvp_autograd(dev(torch, m), dev(torch, v), plan)
+    ho = oracle.gn_hvp(g, m, v)
+    assert rel(host(hv), ho) < 1e-4
+    assert rel(host(hv), host(ag.gn_hvp(dev(torch, m), dev(torch, v), plan))) < 1e-5
+
+
+def test_misfit_only(torch, case):
+    say("entry: fwi_misfit small")
+    g, plan = case["g"], case["plan"]
+    phi = float(plan.misfit(dev(torch, case["m"]), dev(torch, case["dobs"])))
+    phi_o, _ = oracle.misfit_grad(g, case["m"], case["dobs"])
+    assert phi == pytest.approx(phi_o, rel=1e-4)
+
+
+def test_probe_session_graph_replays(torch):
+    """The captured call replayed several times, with eager work and
+    synchronisations in between, matches the eager call every time."""
+    from paper_2507_10804_amd import fwi, probing
+    say("entry: ProbeSession graph capture tiny, B=4")
+    g, m = tiny(nt=160)
+    plan = fwi.Plan(g)
+    combs = synth.impulse_combs(g.nz, g.nx, count=4, spacing=12, seed=100)
+    rad = synth.rademacher_smoothed(g.nz, g.nx, seeds=[200, 201, 202, 203], sigma=2.0)
+    sess = probing.ProbeSession(plan, dev(torch, m), batch=4, use_graph=True)
+    eager = fwi.Plan(g)
+    for rep, batch in enumerate([combs, rad, combs, rad[:3]]):
+        out = host(sess.run(dev(torch, batch)))
+        ref = host(eager.gn_hvp(dev(torch, m), dev(torch, batch)))
+        torch.cuda.synchronize()
+        if batch.shape[0] == 4:
+            assert np.array_equal(out, ref), f"replay {rep} differs from eager"
+        else:  # zero-padded batch: another shot grouping in the adjoint
+            assert rel(out, ref) < 1e-6
+        _ = (dev(torch, batch) * 2).sum().item()  # unrelated eager work in between
+    assert rel(host(sess.run(dev(torch, combs))), oracle.gn_hvp(g, m, combs)) < 1e-4
