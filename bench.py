@@ -129,6 +129,43 @@ def calibrate_copy(nbytes=2 << 30, reps=5):
                       "avg_ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
 
 
+def serve_bench(args):
+    """Serving row: the same seeded closed-loop trace of 32 chains (misfit
+    proposals, single Hessian-vector products and probe batches on three
+    grids with resident models) through the plain one-at-a-time path and
+    through the continuous-batching server; one JSON line."""
+    import torch
+    from paper_2507_10804_amd.serve import Server
+    from paper_2507_10804_amd.serve.backend import GpuBackend
+    from paper_2507_10804_amd.serve import workload as wl
+
+    be = GpuBackend(slots=args.slots, max_batch=16)
+    banks = wl.load_datasets(be)
+    log(f"serving: datasets {list(be.datasets)} resident, budget {be.mem_budget() / 1e9:.0f} GB")
+    out = {"metric": "serving: Hv/s and p50/p99 latency, plain path vs continuous batching",
+           "unit": "Hv/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "32 closed-loop chains, offered 50 req/s; grids 256x128 "
+                                  "(16 shots, 2000 steps), 512x192 (32, 3000), 921x301 "
+                                  "(64, 4000); misfit proposals, single Hv, 1 in 10 a "
+                                  "4-vector probe batch; 4 resident models per grid",
+                      "requests_per_chain": args.requests_per_chain, "slots": args.slots}}
+    for name, slots, coalesce in (("plain", 1, False), ("serving", args.slots, True)):
+        with Server(be, slots=slots, coalesce=coalesce, max_batch=16) as srv:
+            t0 = time.monotonic()
+            recs, tw, t1 = wl.run_closed_loop(srv, be, banks, chains=32, rate=50.0,
+                                              requests_per_chain=args.requests_per_chain,
+                                              seed=args.seed, warmup_s=args.serve_warmup)
+        torch.cuda.synchronize()
+        res = wl.summarize(recs, tw, t1)
+        res["wall_s"] = t1 - t0
+        log(f"{name}: {json.dumps(res)}")
+        out[name] = res
+    out["value"] = out["serving"]["hv_per_s"]
+    out["vs_plain_hv_per_s"] = out["serving"]["hv_per_s"] / max(out["plain"]["hv_per_s"], 1e-12)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,7 +181,15 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
+    ap.add_argument("--mode", choices=["hvp", "serve"], default="hvp")
+    ap.add_argument("--slots", type=int, default=4)
+    ap.add_argument("--requests-per-chain", type=int, default=6)
+    ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--seed", type=int, default=0)
     args = ap.parse_args()
+    if args.mode == "serve":
+        serve_bench(args)
+        return
     if args.calibrate_copy:
         calibrate_copy()
         return

@@ -110,7 +110,9 @@ class Plan:
 
     Methods take and return float32 CUDA tensors (model space [B][nz][nx],
     data space [B][ns][nt][nr]) and enqueue on the current torch stream.
-    Workspaces are cached per (operation, batch); a Plan is not thread-safe.
+    Workspaces are cached per (operation, batch) unless the caller passes its
+    own (``ws=``).  Calls from several threads on different streams are safe
+    when each brings its own workspace and telemetry is off.
     """
 
     def __init__(self, geom, device=None):
@@ -175,16 +177,16 @@ class Plan:
         return ctypes.c_void_p(x.data_ptr())
 
     # -- operations -------------------------------------------------------
-    def forward(self, m):
+    def forward(self, m, ws=None):
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         d = self.torch.empty((g.ns, g.nt, g.nr), dtype=self.torch.float32, device=self.device)
-        ws = self.workspace(FWI_OP_FORWARD)
+        ws = self.workspace(FWI_OP_FORWARD) if ws is None else ws
         _check(self.lib.fwi_forward(self._h, self._p(m), self._p(d), self._p(ws), ws.numel(),
                                     self._stream()))
         return d
 
-    def born(self, m, v):
+    def born(self, m, v, ws=None):
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         v = self._in(v, (g.nz, g.nx), "v")
@@ -192,12 +194,12 @@ class Plan:
         v = v.reshape(-1, g.nz, g.nx)
         B = v.shape[0]
         dd = self.torch.empty((B, g.ns, g.nt, g.nr), dtype=self.torch.float32, device=self.device)
-        ws = self.workspace(FWI_OP_BORN, B)
+        ws = self.workspace(FWI_OP_BORN, B) if ws is None else ws
         _check(self.lib.fwi_born(self._h, self._p(m), self._p(v), B, self._p(dd), self._p(ws),
                                  ws.numel(), self._stream()))
         return dd[0] if single else dd
 
-    def adjoint(self, m, r):
+    def adjoint(self, m, r, ws=None):
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         r = self._in(r, (g.ns, g.nt, g.nr), "r")
@@ -205,7 +207,7 @@ class Plan:
         r = r.reshape(-1, g.ns, g.nt, g.nr)
         B = r.shape[0]
         out = self.torch.empty((B, g.nz, g.nx), dtype=self.torch.float32, device=self.device)
-        ws = self.workspace(FWI_OP_ADJOINT, B)
+        ws = self.workspace(FWI_OP_ADJOINT, B) if ws is None else ws
         _check(self.lib.fwi_adjoint(self._h, self._p(m), self._p(r), B, self._p(out),
                                     self._p(ws), ws.numel(), self._stream()))
         return out[0] if single else out
@@ -237,31 +239,31 @@ class Plan:
         return self.torch.empty(self.workspace_bytes(op, batch), dtype=self.torch.uint8,
                                 device=self.device)
 
-    def misfit(self, m, dobs, out=None):
+    def misfit(self, m, dobs, out=None, ws=None):
         """Phi = 1/2 inv_noise_var |f(m) - dobs|^2 as a device FP64 scalar."""
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         dobs = self._in(dobs, (g.ns, g.nt, g.nr), "dobs")
         phi = out if out is not None else self.torch.empty((), dtype=self.torch.float64,
                                                            device=self.device)
-        ws = self.workspace(FWI_OP_MISFIT)
+        ws = self.workspace(FWI_OP_MISFIT) if ws is None else ws
         _check(self.lib.fwi_misfit(self._h, self._p(m), self._p(dobs), self._p(phi),
                                    self._p(ws), ws.numel(), self._stream()))
         return phi
 
-    def misfit_grad(self, m, dobs):
+    def misfit_grad(self, m, dobs, ws=None):
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         dobs = self._in(dobs, (g.ns, g.nt, g.nr), "dobs")
         phi = self.torch.empty((), dtype=self.torch.float64, device=self.device)
         grad = self.torch.empty((g.nz, g.nx), dtype=self.torch.float32, device=self.device)
-        ws = self.workspace(FWI_OP_MISFIT_GRAD)
+        ws = self.workspace(FWI_OP_MISFIT_GRAD) if ws is None else ws
         _check(self.lib.fwi_misfit_grad(self._h, self._p(m), self._p(dobs), self._p(phi),
                                         self._p(grad), self._p(ws), ws.numel(),
                                         self._stream()))
         return phi, grad
 
-    def gn_hvp(self, m, v, out=None):
+    def gn_hvp(self, m, v, out=None, ws=None):
         g = self.geom
         m = self._in(m, (g.nz, g.nx), "m")
         v = self._in(v, (g.nz, g.nx), "v")
@@ -271,7 +273,7 @@ class Plan:
         hv = out if out is not None else self.torch.empty((B, g.nz, g.nx),
                                                           dtype=self.torch.float32,
                                                           device=self.device)
-        ws = self.workspace(FWI_OP_GN_HVP, B)
+        ws = self.workspace(FWI_OP_GN_HVP, B) if ws is None else ws
         _check(self.lib.fwi_gn_hvp(self._h, self._p(m), self._p(v), B, self._p(hv),
                                    self._p(ws), ws.numel(), self._stream()))
         return hv[0] if single else hv
