@@ -18,6 +18,9 @@ namespace fwi {
 hipError_t launch_step(const Geo &g, const DevTables &t, const StepArgs &a, bool born,
                        hipStream_t st);
 hipError_t launch_adjoint(const Geo &g, const DevTables &t, const AdjArgs &a, hipStream_t st);
+hipError_t launch_step2(const Geo &g, const DevTables &t, const Step2Args &a, bool born,
+                        hipStream_t st);
+hipError_t launch_adjoint2(const Geo &g, const DevTables &t, const Adj2Args &a, hipStream_t st);
 hipError_t launch_setup(const Geo &g, const float *m, const float *v, int B, float *c,
                         float *s2m, float *dc, unsigned int *status, hipStream_t st);
 hipError_t launch_fill(float *p, long long n, hipStream_t st);
@@ -59,7 +62,11 @@ struct fwi_plan {
   // device block image, in int32 words, and offsets into it
   std::vector<int> blk;
   size_t off_status = 0, off_src = 0, off_trp = 0, off_rloc = 0, off_rid = 0, off_tnp = 0,
-         off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0;
+         off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0, off_order = 0;
+  size_t off2[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // two-step tables
+  // advance two time steps per launch (needs K even), per kernel family;
+  // defaults from measurement: only the Born kernel gains
+  bool ts_fwd = false, ts_born = true, ts_adj = false;
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
@@ -82,6 +89,9 @@ struct Layout {
          wseg = 0, mu = 0, img = 0, total = 0;
   int G = 1, group = 1;
 };
+
+// Element offset of the second field set (two-step launches alternate sets).
+size_t set_stride(const Geo &g, int per_shot) { return (size_t)2 * g.ns * per_shot * g.fs; }
 
 int adjoint_group(const fwi_plan *p, int B) {
   if (p->adj_group_override > 0) return std::min(p->adj_group_override, p->geo.ns);
@@ -112,8 +122,11 @@ Layout layout(const fwi_plan *p, int op, int B) {
   L.c = take(F);
   L.s2m = take(F);
   if (needs_dc) L.dc = take(F * B);
-  L.u = take(F * 2 * g.ns);
-  if (needs_dc) L.du = take(F * 2 * g.ns * B);
+  // two-step launches read one field set and write the other
+  const size_t usets = (p->ts_fwd || p->ts_born) ? 2 : 1;
+  const size_t dsets = p->ts_born ? 2 : 1, msets = p->ts_adj ? 2 : 1;
+  L.u = take(F * 2 * g.ns * usets);
+  if (needs_dc) L.du = take(F * 2 * g.ns * B * std::max(dsets, op == FWI_OP_GN_HVP ? msets : 1));
   if (op == FWI_OP_GN_HVP) L.dd = take(ndata * B);
   if (op == FWI_OP_MISFIT_GRAD || op == FWI_OP_MISFIT) {
     L.dres = take(ndata);
@@ -126,7 +139,7 @@ Layout layout(const fwi_plan *p, int op, int B) {
     L.wseg = take(F * g.ns * p->K);
     // the Born fields are dead once the forward sweep is over: the adjoint
     // fields of a Hessian product reuse their memory
-    L.mu = op == FWI_OP_GN_HVP ? L.du : take(F * 2 * g.ns * Badj);
+    L.mu = op == FWI_OP_GN_HVP ? L.du : take(F * 2 * g.ns * Badj * msets);
     L.img = take((size_t)g.fs * sizeof(double) * L.G * Badj);
   }
   L.total = o;
@@ -186,28 +199,56 @@ hipError_t timed(fwi_plan *p, int kind, hipStream_t st, F &&launch) {
   return rc;
 }
 
-// Forward sweep n = 0..nt-2 on the fields at ws+L.u (and Born fields).
+// Checkpoint slot that must receive u^{n}, u^{n-1} when level n starts a
+// segment, or null.
+float *ckpt_slot(const fwi_plan *p, float *ckpt, int n) {
+  if (!ckpt || n % p->K) return nullptr;
+  const int j = n / p->K;
+  return j >= 1 && j < p->nseg ? ckpt + (size_t)j * 2 * p->geo.ns * p->geo.fs : nullptr;
+}
+
+// Forward sweep n = 0..nt-2 on the fields at ws+L.u (and Born fields):
+// pairs of steps per launch while two remain, then single steps.
 int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, float *d_out,
                   float *dd_out, bool store_ckpt, hipStream_t st) {
   const Geo &g = p->geo;
+  float *ckpt = store_ckpt ? at<float>(ws, L.ckpt) : nullptr;
+  float *u = at<float>(ws, L.u), *du = born ? at<float>(ws, L.du) : nullptr;
+  const size_t us = set_stride(g, 1), dus = set_stride(g, B);
+  int cur = 0, n = 0;
+  if (born ? p->ts_born : p->ts_fwd) {
+    Step2Args a{};
+    a.c = at<float>(ws, L.c);
+    a.dc = born ? at<float>(ws, L.dc) : nullptr;
+    a.B = born ? B : 0;
+    a.d_out = d_out;
+    a.dd_out = dd_out;
+    for (; n + 2 <= g.nt - 1; n += 2, cur ^= 1) {
+      a.n = n;
+      a.amp0 = src_amp(p, n);
+      a.amp1 = src_amp(p, n + 1);
+      a.uin = u + cur * us;
+      a.uout = u + (cur ^ 1) * us;
+      a.duin = born ? du + cur * dus : nullptr;
+      a.duout = born ? du + (cur ^ 1) * dus : nullptr;
+      a.ck = ckpt_slot(p, ckpt, n + 2);
+      HIP_TRY(timed(p, born ? FWI_KERNEL_STEP_BORN : FWI_KERNEL_STEP, st,
+                    [&] { return launch_step2(g, p->tabs, a, born, st); }));
+    }
+  }
   StepArgs a{};
   a.c = at<float>(ws, L.c);
   a.dc = born ? at<float>(ws, L.dc) : nullptr;
-  a.u = at<float>(ws, L.u);
-  a.du = born ? at<float>(ws, L.du) : nullptr;
+  a.u = u + cur * us;
+  a.du = born ? du + cur * dus : nullptr;
   a.B = born ? B : 0;
   a.d_out = d_out;
   a.dd_out = dd_out;
   a.order = born ? p->born_order : p->step_order;
-  float *ckpt = store_ckpt ? at<float>(ws, L.ckpt) : nullptr;
-  for (int n = 0; n + 1 < g.nt; ++n) {
+  for (; n + 1 < g.nt; ++n) {
     a.n = n;
     a.src_amp = src_amp(p, n);
-    a.ck = nullptr;
-    if (ckpt && (n + 1) % p->K == 0) {
-      const int j = (n + 1) / p->K;
-      if (j < p->nseg) a.ck = ckpt + (size_t)j * 2 * g.ns * g.fs;
-    }
+    a.ck = ckpt_slot(p, ckpt, n + 1);
     HIP_TRY(timed(p, born ? FWI_KERNEL_STEP_BORN : FWI_KERNEL_STEP, st,
                   [&] { return launch_step(g, p->tabs, a, born, st); }));
   }
@@ -220,41 +261,87 @@ int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, floa
 int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
                   hipStream_t st) {
   const Geo &g = p->geo;
-  HIP_TRY(launch_fill(at<float>(ws, L.mu), (long long)g.fs * 2 * g.ns * B, st));
+  const size_t msets = p->ts_adj ? 2 : 1;
+  const size_t us = set_stride(g, 1), ms = set_stride(g, B);
+  float *u = at<float>(ws, L.u), *mu = at<float>(ws, L.mu);
+  HIP_TRY(launch_fill(mu, (long long)(ms * msets), st));
   HIP_TRY(launch_fill64(at<double>(ws, L.img), (long long)g.fs * L.G * B, st));
-  StepArgs f{};
-  f.c = at<float>(ws, L.c);
-  AdjArgs a{};
-  a.c = at<float>(ws, L.c);
-  a.s2m = at<float>(ws, L.s2m);
-  a.mu = at<float>(ws, L.mu);
-  a.r = r;
-  a.img = at<double>(ws, L.img);
-  a.B = B;
-  a.group = L.group;
-  a.ngroups = L.G;
-  a.order = p->adj_order;
-  f.order = p->step_order;
   float *ckpt = at<float>(ws, L.ckpt);
   float *wseg = at<float>(ws, L.wseg);
+  auto wbuf = [&](int n, int n0) { return wseg + (size_t)(n - n0) * g.ns * g.fs; };
+  int mcur = 0;  // field set holding the adjoint state
   for (int j = p->nseg - 1; j >= 0; --j) {
     const int n0 = j * p->K;
     const int n1 = std::min((j + 1) * p->K, g.nt - 1);
     // recompute on a copy so the checkpoints survive (the adjoint can be
     // repeated after one forward, see fwi_adjoint_resume)
-    f.u = at<float>(ws, L.u);
-    HIP_TRY(launch_copy(f.u, ckpt + (size_t)j * 2 * g.ns * g.fs, (long long)2 * g.ns * g.fs, st));
-    for (int n = n0; n < n1; ++n) {
-      f.n = n;
-      f.src_amp = src_amp(p, n);
-      f.w_out = wseg + (size_t)(n - n0) * g.ns * g.fs;
-      HIP_TRY(timed(p, FWI_KERNEL_STEP, st, [&] { return launch_step(g, p->tabs, f, false, st); }));
+    HIP_TRY(launch_copy(u, ckpt + (size_t)j * 2 * g.ns * g.fs, (long long)us, st));
+    int ucur = 0, n = n0;
+    if (p->ts_fwd) {
+      Step2Args f{};
+      f.c = at<float>(ws, L.c);
+      for (; n + 2 <= n1; n += 2, ucur ^= 1) {
+        f.n = n;
+        f.amp0 = src_amp(p, n);
+        f.amp1 = src_amp(p, n + 1);
+        f.uin = u + ucur * us;
+        f.uout = u + (ucur ^ 1) * us;
+        f.w_out0 = wbuf(n, n0);
+        f.w_out1 = wbuf(n + 1, n0);
+        HIP_TRY(timed(p, FWI_KERNEL_STEP, st,
+                      [&] { return launch_step2(g, p->tabs, f, false, st); }));
+      }
     }
-    const int ktop = (j == p->nseg - 1) ? g.nt - 1 : n1 - 1;
-    for (int k = ktop; k >= n0; --k) {
-      a.k = k;
-      a.w = (k <= g.nt - 2) ? wseg + (size_t)(k - n0) * g.ns * g.fs : nullptr;
-      HIP_TRY(timed(p, FWI_KERNEL_ADJOINT, st, [&] { return launch_adjoint(g, p->tabs, a, st); }));
+    if (n < n1) {
+      StepArgs f{};
+      f.c = at<float>(ws, L.c);
+      f.u = u + ucur * us;
+      f.order = p->step_order;
+      for (; n < n1; ++n) {
+        f.n = n;
+        f.src_amp = src_amp(p, n);
+        f.w_out = wbuf(n, n0);
+        HIP_TRY(timed(p, FWI_KERNEL_STEP, st,
+                      [&] { return launch_step(g, p->tabs, f, false, st); }));
+      }
+    }
+    int k = (j == p->nseg - 1) ? g.nt - 1 : n1 - 1;
+    if (p->ts_adj) {
+      Adj2Args a{};
+      a.c = at<float>(ws, L.c);
+      a.s2m = at<float>(ws, L.s2m);
+      a.r = r;
+      a.img = at<double>(ws, L.img);
+      a.B = B;
+      a.group = L.group;
+      a.ngroups = L.G;
+      for (; k - 1 >= n0; k -= 2, mcur ^= 1) {
+        a.k = k;
+        a.muin = mu + mcur * ms;
+        a.muout = mu + (mcur ^ 1) * ms;
+        a.w0 = (k <= g.nt - 2) ? wbuf(k, n0) : nullptr;
+        a.w1 = wbuf(k - 1, n0);
+        HIP_TRY(timed(p, FWI_KERNEL_ADJOINT, st,
+                      [&] { return launch_adjoint2(g, p->tabs, a, st); }));
+      }
+    }
+    if (k >= n0) {
+      AdjArgs a{};
+      a.c = at<float>(ws, L.c);
+      a.s2m = at<float>(ws, L.s2m);
+      a.mu = mu + mcur * ms;
+      a.r = r;
+      a.img = at<double>(ws, L.img);
+      a.B = B;
+      a.group = L.group;
+      a.ngroups = L.G;
+      a.order = p->adj_order;
+      for (; k >= n0; --k) {
+        a.k = k;
+        a.w = (k <= g.nt - 2) ? wbuf(k, n0) : nullptr;
+        HIP_TRY(timed(p, FWI_KERNEL_ADJOINT, st,
+                      [&] { return launch_adjoint(g, p->tabs, a, st); }));
+      }
     }
   }
   return FWI_OK;
@@ -265,8 +352,8 @@ int prologue(fwi_plan *p, const Layout &L, void *ws, const float *m, const float
   const Geo &g = p->geo;
   HIP_TRY(launch_setup(g, m, v, B, at<float>(ws, L.c), at<float>(ws, L.s2m),
                        born ? at<float>(ws, L.dc) : nullptr, p->tabs.status, st));
-  HIP_TRY(launch_fill(at<float>(ws, L.u), (long long)g.fs * 2 * g.ns, st));
-  if (born) HIP_TRY(launch_fill(at<float>(ws, L.du), (long long)g.fs * 2 * g.ns * B, st));
+  HIP_TRY(launch_fill(at<float>(ws, L.u), (long long)set_stride(g, 1), st));
+  if (born) HIP_TRY(launch_fill(at<float>(ws, L.du), (long long)set_stride(g, B), st));
   if (adj) HIP_TRY(launch_fill(at<float>(ws, L.ckpt), (long long)g.fs * 2 * g.ns, st));
   return FWI_OK;
 }
@@ -357,9 +444,9 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   p->wavelet.assign(G.wavelet, G.wavelet + G.nt);
   // tuning knobs for experiments; the defaults are the measured best
   if (const char *e = std::getenv("FWI_ADJ_GROUP")) p->adj_group_override = std::atoi(e);
-  if (const char *e = std::getenv("FWI_STEP_ORDER")) p->step_order = std::atoi(e) != 0;
-  if (const char *e = std::getenv("FWI_BORN_ORDER")) p->born_order = std::atoi(e) != 0;
-  if (const char *e = std::getenv("FWI_ADJ_ORDER")) p->adj_order = std::atoi(e) != 0;
+  if (const char *e = std::getenv("FWI_STEP_ORDER")) p->step_order = std::atoi(e);
+  if (const char *e = std::getenv("FWI_BORN_ORDER")) p->born_order = std::atoi(e);
+  if (const char *e = std::getenv("FWI_ADJ_ORDER")) p->adj_order = std::atoi(e);
 
   // receiver tables: sort receivers by (tile, local index, number)
   std::vector<std::tuple<int, int, int, long long>> recs;  // tile, local, id, gidx
@@ -391,9 +478,9 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   }
   nrp.push_back((int)nrec.size());
   for (int t = 0; t < g.ntiles; ++t) tnp[t + 1] += tnp[t];
-  if ((long long)g.fs > 2147483647LL) {
+  if ((long long)g.fs * (long long)sizeof(double) > 2147483647LL) {
     delete p;
-    return fail(FWI_EINVAL, "padded field too large for 32-bit node indices");
+    return fail(FWI_EINVAL, "padded field too large for 32-bit byte offsets");
   }
 
   // device block image
@@ -419,6 +506,81 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   p->off_ngidx = put(ngidx);
   p->off_nrp = put(nrp);
   p->off_nrec = put(nrec);
+  // blocked workgroup order: bx x bz rectangles of tiles, row by row
+  int bx = 2, bz = 2;
+  if (const char *e = std::getenv("FWI_BLOCK_X")) bx = std::max(1, std::atoi(e));
+  if (const char *e = std::getenv("FWI_BLOCK_Z")) bz = std::max(1, std::atoi(e));
+  std::vector<int> order;
+  for (int z0 = 0; z0 < g.tiles_z; z0 += bz)
+    for (int x0 = 0; x0 < g.tiles_x; x0 += bx)
+      for (int z = z0; z < std::min(z0 + bz, g.tiles_z); ++z)
+        for (int x = x0; x < std::min(x0 + bx, g.tiles_x); ++x) order.push_back(z * g.tiles_x + x);
+  g.blk = bx * bz;
+  g.nblocks = (g.ntiles + g.blk - 1) / g.blk;
+  p->off_order = put(order);
+
+  // two-step tiling and its receiver tables
+  g.tiles_x2 = (int)((nxp + TX2 - 1) / TX2);
+  g.tiles_z2 = (int)((nzp + TZ2 - 1) / TZ2);
+  g.ntiles2 = g.tiles_x2 * g.tiles_z2;
+  {
+    std::vector<int> rp(g.ntiles2 + 1, 0), rloc2, rid2, np2(g.ntiles2 + 1, 0), nloc2, ngid2,
+        nrp2, nrec2;
+    // distinct receiver nodes and the receivers on each
+    std::vector<std::tuple<int, int, int>> byn;  // i, j, receiver
+    for (int r = 0; r < G.nr; ++r)
+      byn.emplace_back(G.rec_zx[2 * r] + G.nb, G.rec_zx[2 * r + 1] + G.nb, r);
+    std::sort(byn.begin(), byn.end());
+    for (int t2 = 0; t2 < g.ntiles2; ++t2) {
+      const int i0 = (t2 / g.tiles_x2) * TZ2, j0 = (t2 % g.tiles_x2) * TX2;
+      for (size_t q = 0; q < byn.size(); ++q) {
+        const int i = std::get<0>(byn[q]), j = std::get<1>(byn[q]);
+        const int le = (i - i0 + HALO) * EX + (j - j0 + HALO);
+        if (i >= i0 && i < i0 + TZ2 && j >= j0 && j < j0 + TX2) {
+          rloc2.push_back(le);
+          rid2.push_back(std::get<2>(byn[q]));
+          rp[t2 + 1]++;
+        }
+        const bool fresh = q == 0 || std::get<0>(byn[q - 1]) != i || std::get<1>(byn[q - 1]) != j;
+        if (fresh && i >= i0 - HALO && i < i0 + TZ2 + HALO && j >= j0 - HALO &&
+            j < j0 + TX2 + HALO) {
+          nloc2.push_back(le);
+          ngid2.push_back(i * g.pitch + j);
+          nrp2.push_back((int)nrec2.size());
+          for (size_t q2 = q; q2 < byn.size() && std::get<0>(byn[q2]) == i &&
+                              std::get<1>(byn[q2]) == j;
+               ++q2)
+            nrec2.push_back(std::get<2>(byn[q2]));
+          np2[t2 + 1]++;
+        }
+      }
+    }
+    nrp2.push_back((int)nrec2.size());
+    for (int t2 = 0; t2 < g.ntiles2; ++t2) {
+      rp[t2 + 1] += rp[t2];
+      np2[t2 + 1] += np2[t2];
+    }
+    p->off2[0] = put(rp);
+    p->off2[1] = put(rloc2);
+    p->off2[2] = put(rid2);
+    p->off2[3] = put(np2);
+    p->off2[4] = put(nloc2);
+    p->off2[5] = put(ngid2);
+    p->off2[6] = put(nrp2);
+    p->off2[7] = put(nrec2);
+  }
+  // FWI_TWO_STEP: three 0/1 digits for forward, Born, adjoint (tuning knob)
+  if (const char *e = std::getenv("FWI_TWO_STEP")) {
+    const std::string f(e);
+    if (f.size() == 3) {
+      p->ts_fwd = f[0] == '1';
+      p->ts_born = f[1] == '1';
+      p->ts_adj = f[2] == '1';
+    } else {
+      p->ts_fwd = p->ts_born = p->ts_adj = std::atoi(e) != 0;
+    }
+  }
+  if (p->K % 2) p->ts_fwd = p->ts_born = p->ts_adj = false;
   *out = p;
   return FWI_OK;
 }
@@ -465,6 +627,15 @@ int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream) {
   t.node_gidx = base + p->off_ngidx;
   t.node_rec_ptr = base + p->off_nrp;
   t.node_recs = base + p->off_nrec;
+  t.tile_order = base + p->off_order;
+  t.t2_rec_ptr = base + p->off2[0];
+  t.t2_rec_local = base + p->off2[1];
+  t.t2_rec_id = base + p->off2[2];
+  t.t2_node_ptr = base + p->off2[3];
+  t.t2_node_local = base + p->off2[4];
+  t.t2_node_gidx = base + p->off2[5];
+  t.t2_node_rec_ptr = base + p->off2[6];
+  t.t2_node_recs = base + p->off2[7];
   return FWI_OK;
 }
 

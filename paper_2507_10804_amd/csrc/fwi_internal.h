@@ -18,6 +18,20 @@ constexpr int LW = TX + 2 * HALO;  // LDS row width
 constexpr int LH = TZ + 2 * HALO;  // LDS rows
 constexpr int NTHREADS = TX * NWAVE;
 
+// Two-step (temporally blocked) tiles: TX2 x TZ2 outputs; the intermediate
+// time level is computed on the tile plus a HALO ring (EX x EZ, one wave64
+// row per tile row) and the input level is staged with a 2*HALO ring.
+constexpr int TX2 = TX - 2 * HALO;      // 56 output columns
+constexpr int TZ2 = TZ;                 // 32 output rows
+constexpr int EX = TX2 + 2 * HALO;      // 64
+constexpr int EZ = TZ2 + 2 * HALO;      // 40
+constexpr int IX = TX2 + 4 * HALO;      // 72
+constexpr int IZ = TZ2 + 4 * HALO;      // 48
+constexpr int NWAVE2 = 8;               // wavefronts per two-step workgroup
+constexpr int NTHREADS2 = TX * NWAVE2;  // 512
+constexpr int RA = EZ / NWAVE2;         // 5 intermediate rows per wavefront
+constexpr int RB = TZ2 / NWAVE2;        // 4 output rows per wavefront
+
 // Largest Courant number max(m) dt/dx the scheme tolerates.
 constexpr float CFL_LIMIT = 0.5546f;
 
@@ -35,6 +49,9 @@ struct Geo {
   float kmax, inv_nb;
   float c1, c2, c3, c4;  // C1..C4 of the stencil, divided by dx^2 (C0 = -2 sum)
   float dt, inv_dx;
+  int blk;       // tiles per block in the blocked workgroup order
+  int nblocks;   // ceil(ntiles / blk)
+  int tiles_x2, tiles_z2, ntiles2;  // two-step tiling
 };
 
 // Device block of a plan (offsets in int32 units from its base).
@@ -48,7 +65,50 @@ struct DevTables {
   const int *node_gidx;     // i*pitch + j of each node
   const int *node_rec_ptr;  // nnodes+1: receivers sitting on node k
   const int *node_recs;     // receiver numbers, grouped by node
+  const int *tile_order;    // ntiles: tiles listed block by block (blocked order)
+  // two-step tiling: receivers inside each output tile (E-local index
+  // (i - i0 + HALO) * EX + (j - j0 + HALO)), and distinct receiver nodes
+  // inside each tile's extended region, for injection
+  const int *t2_rec_ptr, *t2_rec_local, *t2_rec_id;
+  const int *t2_node_ptr, *t2_node_local, *t2_node_gidx, *t2_node_rec_ptr, *t2_node_recs;
   unsigned int *status;     // FWI_STATUS_* bits
+};
+
+// Arguments of one two-step forward / forward+Born launch (n even):
+// reads (u^n, u^{n-1}) from `uin`, writes (u^{n+1}, u^{n+2}) to `uout`,
+// both [ns][2][fs] with u^k in slot k & 1; Born fields likewise per vector.
+struct Step2Args {
+  const float *c;
+  const float *dc;
+  const float *uin;
+  float *uout;
+  const float *duin;   // [ns][B][2][fs]
+  float *duout;
+  float *w_out0;       // [ns][fs] receives w^n, or null
+  float *w_out1;       // [ns][fs] receives w^{n+1}, or null
+  float *d_out;        // [ns][nt][nr] receives R u^{n+1}, R u^{n+2}, or null
+  float *dd_out;       // [B][ns][nt][nr], or null
+  float *ck;           // [ns][2][fs]: receives (u^{n+1}, u^{n+2}), or null
+  int n;
+  int B;
+  float amp0, amp1;    // s(n dt)/dx^2, s((n+1) dt)/dx^2
+};
+
+// Arguments of one two-step adjoint launch: (mu^{k+1}, mu^{k+2}) from `muin`
+// to (mu^k, mu^{k-1}) in `muout`, image terms n = k (if w0) and n = k-1.
+struct Adj2Args {
+  const float *c;
+  const float *s2m;
+  const float *muin;   // [B][ns][2][fs]
+  float *muout;
+  const float *w0;     // [ns][fs] w^k, or null (k = nt-1: no image term)
+  const float *w1;     // [ns][fs] w^{k-1}
+  const float *r;      // [B][ns][nt][nr]
+  double *img;         // [G][B][fs]
+  int k;
+  int B;
+  int group;
+  int ngroups;
 };
 
 // Arguments of one forward / forward+Born time step.
@@ -64,7 +124,7 @@ struct StepArgs {
   int n;              // step: computes u^{n+1}
   int B;
   float src_amp;      // s(n dt) / dx^2
-  int order;          // workgroup order: 0 shot-major, 1 tile-major
+  int order;          // workgroup order: 0 shot-major, 1 tile-major, 2 blocked
 };
 
 // Arguments of one adjoint + imaging time step (mu = c * lambda form).
@@ -79,7 +139,7 @@ struct AdjArgs {
   int B;
   int group;          // shots per workgroup
   int ngroups;
-  int order;          // workgroup order: 0 vector-major, 1 tile-major
+  int order;          // workgroup order: 0 vector-major, 1 tile-major, 2 blocked
 };
 
 }  // namespace fwi

@@ -31,6 +31,32 @@ __device__ __forceinline__ int xcd_remap(int bid, int n) {
   return (x < rem) ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
 }
 
+// Loads and stores at an element offset from a workgroup-uniform base, as
+// raw buffer accesses: the base lives in a scalar buffer descriptor and each
+// access needs one 32-bit byte offset in a vector register (plain pointers
+// cost a 64-bit address per access).  The plan bounds every per-field byte
+// offset below 2^31.  Descriptor word 3 is the gfx9-family raw-buffer format.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
+}
+__device__ __forceinline__ float ldf(const float *base, unsigned e) {
+  return __builtin_bit_cast(float,
+                            __builtin_amdgcn_raw_buffer_load_b32(rsrc(base), (int)(e << 2), 0, 0));
+}
+__device__ __forceinline__ void stf(float *base, unsigned e, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rsrc(base), (int)(e << 2),
+                                        0, 0);
+}
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double ldd(const double *base, unsigned e) {
+  return __builtin_bit_cast(double,
+                            __builtin_amdgcn_raw_buffer_load_b64(rsrc(base), (int)(e << 3), 0, 0));
+}
+__device__ __forceinline__ void std_(double *base, unsigned e, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rsrc(base), (int)(e << 3),
+                                        0, 0);
+}
+
 __device__ __forceinline__ float sponge_kappa(const Geo &g, int i, int j) {
   const int dxc = max(max(g.nb - j, 0), j - (g.nxp - 1 - g.nb));
   const int dzc = max(max(g.nb - i, 0), i - (g.nzp - 1 - g.nb));
@@ -46,6 +72,23 @@ __device__ __forceinline__ void sponge_ab(const Geo &g, int i, int j, float &a2,
   const float inv = __builtin_amdgcn_rcpf(1.0f + kap);
   a2 = 2.0f * inv;
   b = (1.0f - kap) * inv;
+}
+
+// True when every cell of the tile whose top-left cell is (i0, j0) lies in
+// the undamped interior, where a = b = 1 exactly (workgroup-uniform).
+__device__ __forceinline__ bool tile_interior(const Geo &g, int i0, int j0, int tz, int tx) {
+  return i0 >= g.nb && i0 + tz <= g.nzp - g.nb && j0 >= g.nb && j0 + tx <= g.nxp - g.nb;
+}
+
+// 2a and b, skipping the sponge arithmetic on interior tiles (same values).
+__device__ __forceinline__ void coef_ab(const Geo &g, bool interior, int i, int j, float &a2,
+                                        float &b) {
+  if (interior) {
+    a2 = 2.0f;
+    b = 1.0f;
+  } else {
+    sponge_ab(g, i, j, a2, b);
+  }
 }
 
 // One damped leapfrog update, a2 u - b u_prev + c w, in a fixed evaluation
@@ -80,12 +123,12 @@ __device__ __forceinline__ void fetch_tile(TileRegs &T, const float *__restrict_
     const int ic = min(max(i, 0), g.nzp - 1);
     // multiply by a 0/1 mask instead of selecting: the load stays
     // unconditional (a select lets the compiler sink it into a branch)
-    T.v[q] = f[ic * g.pitch + jc] * ((jok && i >= 0 && i < g.nzp) ? 1.0f : 0.0f);
+    T.v[q] = ldf(f, (unsigned)(ic * g.pitch + jc)) * ((jok && i >= 0 && i < g.nzp) ? 1.0f : 0.0f);
   }
   const int r = tid / (2 * HALO), c = tid % (2 * HALO);
   const int col = c < HALO ? c - HALO : TX + c - HALO;
   const int i = i0 + r, jj = j0 + col;
-  T.h = f[min(i, g.nzp - 1) * g.pitch + min(max(jj, 0), g.nxp - 1)] *
+  T.h = ldf(f, (unsigned)(min(i, g.nzp - 1) * g.pitch + min(max(jj, 0), g.nxp - 1))) *
         ((i < g.nzp && jj >= 0 && jj < g.nxp) ? 1.0f : 0.0f);
 }
 
@@ -147,14 +190,27 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   // order 0: shot-major (neighbouring tiles of one shot are adjacent ids);
   // order 1: tile-major (the shots of one tile are adjacent ids, so operands
-  // shared by all shots, such as the Born coefficients, are reused from L2)
-  const int s = a.order ? lid % g.ns : lid / g.ntiles;
-  const int tile = a.order ? lid / g.ns : lid - s * g.ntiles;
+  // shared by all shots, such as the Born coefficients, are reused from L2);
+  // order 2: blocked -- a block of neighbouring tiles for every shot, block
+  // after block, which keeps both the shared tiles and the halos in L2
+  int s, tile;
+  if (a.order == 2) {
+    const int per = g.blk * g.ns;
+    const int blk = lid / per, rem = lid - blk * per;
+    s = rem / g.blk;
+    const int p = blk * g.blk + (rem - s * g.blk);
+    if (p >= g.ntiles) return;  // padding of the last block (whole workgroup)
+    tile = t.tile_order[p];
+  } else {
+    s = a.order ? lid % g.ns : lid / g.ntiles;
+    tile = a.order ? lid / g.ns : lid - s * g.ntiles;
+  }
   const int tzi = tile / g.tiles_x, txi = tile - tzi * g.tiles_x;
   const int i0 = tzi * TZ, j0 = txi * TX;
   const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
   const int j = j0 + lane, ib = i0 + wv * RZ;
   const long long fs = g.fs;
+  const bool inner = tile_interior(g, i0, j0, TZ, TX);
 
   float *ubase = a.u + (long long)s * 2 * fs;
   const float *un = ubase + (a.n & 1) * fs;
@@ -164,15 +220,15 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
   // columns outside the grid read a clamped element and store nothing
   const int jc = min(j, g.nxp - 1);
   const bool jok = j < g.nxp;
-  int idx[RZ];
+  unsigned idx[RZ];
   float cc[RZ], unew[RZ], um[RZ];
   TileRegs T;
   fetch_tile(T, un, i0, j0, g, tid);
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    idx[r] = min(ib + r, g.nzp - 1) * g.pitch + jc;
-    cc[r] = a.c[idx[r]];
-    um[r] = uo[idx[r]];
+    idx[r] = (unsigned)(min(ib + r, g.nzp - 1) * g.pitch + jc);
+    cc[r] = ldf(a.c, idx[r]);
+    um[r] = ldf(uo, idx[r]);
   }
   commit_tile(L, T, tid);
   __syncthreads();
@@ -193,14 +249,14 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
     const int i = ib + r;
     const bool ok = jok && i < g.nzp;
     float a2, bb;
-    sponge_ab(g, i, j, a2, bb);
+    coef_ab(g, inner, i, j, a2, bb);
     unew[r] = leapfrog(a2, bb, ctr[r], um[r], cc[r], w[r]);
     if (ok) {
-      uo[idx[r]] = unew[r];
-      if (a.w_out) a.w_out[s * fs + idx[r]] = w[r];
+      stf(uo, idx[r], unew[r]);
+      if (a.w_out) stf(a.w_out + s * fs, idx[r], w[r]);
       if (a.ck) {
-        a.ck[(2 * s + ((a.n + 1) & 1)) * fs + idx[r]] = unew[r];
-        a.ck[(2 * s + (a.n & 1)) * fs + idx[r]] = ctr[r];
+        stf(a.ck + (2 * s + ((a.n + 1) & 1)) * fs, idx[r], unew[r]);
+        stf(a.ck + (2 * s + (a.n & 1)) * fs, idx[r], ctr[r]);
       }
     }
   }
@@ -221,8 +277,8 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
       fetch_tile(D, dn, i0, j0, g, tid);
 #pragma unroll
       for (int r = 0; r < RZ; ++r) {
-        dm[r] = dout[idx[r]];
-        dcv[r] = dcb[idx[r]];
+        dm[r] = ldf(dout, idx[r]);
+        dcv[r] = ldf(dcb, idx[r]);
       }
       __syncthreads();
       commit_tile(L, D, tid);
@@ -233,9 +289,9 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
         const int i = ib + r;
         const bool ok = jok && i < g.nzp;
         float a2, bb;
-        sponge_ab(g, i, j, a2, bb);
+        coef_ab(g, inner, i, j, a2, bb);
         dnew[r] = __builtin_fmaf(dcv[r], w[r], leapfrog(a2, bb, dctr[r], dm[r], cc[r], lap[r]));
-        if (ok) dout[idx[r]] = dnew[r];
+        if (ok) stf(dout, idx[r], dnew[r]);
       }
       if (a.dd_out && rp1 > rp0)
         gather_receivers(L, dnew, t, rp0, rp1, tid,
@@ -255,7 +311,17 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
   // index fastest, so the forward wavefield w of a shot group (shared by all
   // vectors) is reused from L2 by consecutive workgroups
   int tile, b, grp;
-  if (a.order) {
+  if (a.order == 2) {
+    const int nb = a.B * a.ngroups;
+    const int per = g.blk * nb;
+    const int blk = lid / per, rem = lid - blk * per;
+    const int item = rem / g.blk;  // vector fastest within the batch items
+    b = item % a.B;
+    grp = item / a.B;
+    const int p = blk * g.blk + (rem - item * g.blk);
+    if (p >= g.ntiles) return;  // padding of the last block (whole workgroup)
+    tile = t.tile_order[p];
+  } else if (a.order) {
     b = lid % a.B;
     grp = (lid / a.B) % a.ngroups;
     tile = lid / (a.B * a.ngroups);
@@ -270,15 +336,16 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
   const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
   const int j = j0 + lane, ib = i0 + wv * RZ;
   const long long fs = g.fs;
+  const bool inner = tile_interior(g, i0, j0, TZ, TX);
 
   const int jc = min(j, g.nxp - 1);
   const bool jok = j < g.nxp;
   float cc[RZ], img[RZ];
-  int idx[RZ];
+  unsigned idx[RZ];
 #pragma unroll
   for (int r = 0; r < RZ; ++r) {
-    idx[r] = min(ib + r, g.nzp - 1) * g.pitch + jc;
-    cc[r] = a.c[idx[r]];
+    idx[r] = (unsigned)(min(ib + r, g.nzp - 1) * g.pitch + jc);
+    cc[r] = ldf(a.c, idx[r]);
     img[r] = 0.0f;
   }
   const int np0 = t.tile_node_ptr[tile], np1 = t.tile_node_ptr[tile + 1];
@@ -295,8 +362,8 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
     fetch_tile(T, m1, i0, j0, g, tid);
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
-      m2[r] = m0[idx[r]];
-      wv_[r] = ws_ ? ws_[idx[r]] : 0.0f;
+      m2[r] = ldf(m0, idx[r]);
+      wv_[r] = ws_ ? ldf(ws_, idx[r]) : 0.0f;
     }
     if (s > s0) __syncthreads();
     commit_tile(L, T, tid);
@@ -305,7 +372,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
       float a2, bb;
-      sponge_ab(g, ib + r, j, a2, bb);
+      coef_ab(g, inner, ib + r, j, a2, bb);
       out[r] = leapfrog(a2, bb, ctr[r], m2[r], cc[r], lap[r]);
       img[r] = __builtin_fmaf(wv_[r], ctr[r], img[r]);
     }
@@ -326,7 +393,7 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
     }
 #pragma unroll
     for (int r = 0; r < RZ; ++r)
-      if (jok && ib + r < g.nzp) m0[idx[r]] = out[r];
+      if (jok && ib + r < g.nzp) stf(m0, idx[r], out[r]);
   }
   if (a.w) {
     double *ig = a.img + ((long long)grp * a.B + b) * fs;
@@ -334,13 +401,406 @@ __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArg
     float sm[RZ];
 #pragma unroll
     for (int r = 0; r < RZ; ++r) {
-      old[r] = ig[idx[r]];
-      sm[r] = a.s2m[idx[r]];
+      old[r] = ldd(ig, idx[r]);
+      sm[r] = ldf(a.s2m, idx[r]);
     }
 #pragma unroll
     for (int r = 0; r < RZ; ++r)
-      if (jok && ib + r < g.nzp) ig[idx[r]] = old[r] + (double)sm[r] * (double)img[r];
+      if (jok && ib + r < g.nzp) std_(ig, idx[r], old[r] + (double)sm[r] * (double)img[r]);
   }
+}
+
+// ----------------------------------------------------------------------
+// Two time steps per launch (temporal blocking).  Per tile of TX2 x TZ2
+// outputs: the input level is staged in LDS with a 2*HALO ring (IX x IZ), the
+// intermediate level is computed on the tile plus a HALO ring (EX x EZ: lane
+// = column, RA rows per wavefront) into LDS, and the second step produces the
+// outputs (lanes HALO..HALO+TX2-1, RB rows per wavefront).  Each field is
+// read twice and written twice per two steps, against three accesses per
+// step for single steps.  Points outside the padded grid are zero, as in the
+// one-step kernels, and every load is unconditional from a clamped address.
+
+struct Tile2Regs {
+  float v[IZ / NWAVE2];  // core 64 columns, 6 rows per wavefront
+  float x;               // the 8 extra columns x 48 rows, one value per thread
+};
+
+static_assert(IZ % NWAVE2 == 0 && EZ % NWAVE2 == 0 && TZ2 % NWAVE2 == 0, "rows per wavefront");
+static_assert(IZ * (IX - TX) <= NTHREADS2, "extra columns: at most one value per thread");
+
+__device__ __forceinline__ float masked_load(const float *__restrict__ f, int i, int j,
+                                             const Geo &g) {
+  const int ic = min(max(i, 0), g.nzp - 1), jc = min(max(j, 0), g.nxp - 1);
+  return ldf(f, (unsigned)(ic * g.pitch + jc)) *
+         ((i >= 0 && i < g.nzp && j >= 0 && j < g.nxp) ? 1.0f : 0.0f);
+}
+
+// Input level on rows i0-2H..i0+TZ2+2H-1, columns j0-2H..j0+TX2+2H-1.
+__device__ __forceinline__ void fetch_tile2(Tile2Regs &T, const float *__restrict__ f, int i0,
+                                            int j0, const Geo &g, int tid) {
+  const int lane = tid % TX, wv = tid / TX;
+#pragma unroll
+  for (int q = 0; q < IZ / NWAVE2; ++q)
+    T.v[q] = masked_load(f, i0 - 2 * HALO + wv + q * NWAVE2, j0 - 2 * HALO + lane, g);
+  const int c = tid % (IX - TX), r = min(tid / (IX - TX), IZ - 1);
+  T.x = masked_load(f, i0 - 2 * HALO + r, j0 - 2 * HALO + TX + c, g);
+}
+
+__device__ __forceinline__ void commit_tile2(float *__restrict__ LI, const Tile2Regs &T,
+                                             int tid) {
+  const int lane = tid % TX, wv = tid / TX;
+#pragma unroll
+  for (int q = 0; q < IZ / NWAVE2; ++q) LI[(wv + q * NWAVE2) * IX + lane] = T.v[q];
+  const int c = tid % (IX - TX), r = tid / (IX - TX);
+  if (r < IZ) LI[r * IX + TX + c] = T.x;
+}
+
+// L at the RA intermediate points of this thread (E row wv*RA + r, column
+// lane), from the staged input level; ctr = centre values.
+__device__ __forceinline__ void lap_stepA(const float *__restrict__ LI, const Geo &g, int lane,
+                                          int wv, float (&lap)[RA], float (&ctr)[RA]) {
+  float col[RA + 2 * HALO];
+#pragma unroll
+  for (int q = 0; q < RA + 2 * HALO; ++q) col[q] = LI[(wv * RA + q) * IX + HALO + lane];
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const float *row = LI + (wv * RA + r + HALO) * IX + HALO + lane;
+    const float u = col[r + HALO];
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = HALO; k >= 1; --k) {
+      const float sk = ((col[r + HALO - k] - u) + (col[r + HALO + k] - u)) +
+                       ((row[-k] - u) + (row[k] - u));
+      const float ck = k == 1 ? g.c1 : k == 2 ? g.c2 : k == 3 ? g.c3 : g.c4;
+      acc = __builtin_fmaf(ck, sk, acc);
+    }
+    lap[r] = acc;
+    ctr[r] = u;
+  }
+}
+
+// L at the RB output points of this thread (E row wv*RB + r + HALO, column
+// lb), from the intermediate level in LE.  lb is the lane clamped into the
+// output columns so that every LDS address stays inside the row.
+__device__ __forceinline__ void lap_stepB(const float *__restrict__ LE, const Geo &g, int lb,
+                                          int wv, float (&lap)[RB], float (&ctr)[RB]) {
+  float col[RB + 2 * HALO];
+#pragma unroll
+  for (int q = 0; q < RB + 2 * HALO; ++q) col[q] = LE[(wv * RB + q) * EX + lb];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const float *row = LE + (wv * RB + r + HALO) * EX + lb;
+    const float u = col[r + HALO];
+    float acc = 0.0f;
+#pragma unroll
+    for (int k = HALO; k >= 1; --k) {
+      const float sk = ((col[r + HALO - k] - u) + (col[r + HALO + k] - u)) +
+                       ((row[-k] - u) + (row[k] - u));
+      const float ck = k == 1 ? g.c1 : k == 2 ? g.c2 : k == 3 ? g.c3 : g.c4;
+      acc = __builtin_fmaf(ck, sk, acc);
+    }
+    lap[r] = acc;
+    ctr[r] = u;
+  }
+}
+
+// Values of the output points written into LE (at their E positions), then
+// gathered at the tile's receivers.
+__device__ __forceinline__ void gather2(float *__restrict__ LE, const float (&val)[RB],
+                                        bool colT, int lane, int wv, const DevTables &t, int rp0,
+                                        int rp1, int tid, float *__restrict__ dst) {
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (colT) LE[(wv * RB + r + HALO) * EX + lane] = val[r];
+  __syncthreads();
+  for (int e = rp0 + tid; e < rp1; e += NTHREADS2) dst[t.t2_rec_id[e]] = LE[t.t2_rec_local[e]];
+}
+
+template <bool BORN>
+__global__ __launch_bounds__(NTHREADS2) void k_step2(Geo g, DevTables t, Step2Args a) {
+  __shared__ float LI[IZ * IX];
+  __shared__ float LE[EZ * EX];
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int s = lid / g.ntiles2, tile = lid - s * g.ntiles2;
+  const int tzi = tile / g.tiles_x2, txi = tile - tzi * g.tiles_x2;
+  const int i0 = tzi * TZ2, j0 = txi * TX2;
+  const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
+  const long long fs = g.fs;
+  const bool inner = tile_interior(g, i0 - HALO, j0 - HALO, EZ, EX);
+
+  const int jE = j0 - HALO + lane;  // column of this lane (E and output)
+  const bool colE = jE >= 0 && jE < g.nxp;
+  const bool colT = lane >= HALO && lane < HALO + TX2 && colE;
+  const int jc = min(max(jE, 0), g.nxp - 1);
+  const int lb = min(max(lane, HALO), EX - 1 - HALO);
+  const int iA = i0 - HALO + wv * RA;  // first intermediate row of this thread
+  const int iB = i0 + wv * RB;         // first output row of this thread
+
+  const float *un = a.uin + (2 * s + (a.n & 1)) * fs;
+  const float *um = a.uin + (2 * s + ((a.n + 1) & 1)) * fs;
+  float *o1 = a.uout + (2 * s + ((a.n + 1) & 1)) * fs;  // u^{n+1}
+  float *o2 = a.uout + (2 * s + (a.n & 1)) * fs;        // u^{n+2}
+
+  unsigned idxA[RA], idxB[RB];
+  float cA[RA], cB[RB], umA[RA], unB[RB];
+  Tile2Regs T;
+  fetch_tile2(T, un, i0, j0, g, tid);
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    idxA[r] = (unsigned)(min(max(iA + r, 0), g.nzp - 1) * g.pitch + jc);
+    cA[r] = ldf(a.c, idxA[r]);
+    umA[r] = ldf(um, idxA[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    idxB[r] = (unsigned)(min(iB + r, g.nzp - 1) * g.pitch + jc);
+    cB[r] = ldf(a.c, idxB[r]);
+  }
+  commit_tile2(LI, T, tid);
+  __syncthreads();
+
+  const int si = t.src_ij[2 * s], sj = t.src_ij[2 * s + 1];
+  // step A: w^n and u^{n+1} on the extended region
+  float wA[RA], ctrA[RA];
+  lap_stepA(LI, g, lane, wv, wA, ctrA);
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    const int i = iA + r;
+    if (jE == sj && i == si) wA[r] += a.amp0;
+    float a2, bb;
+    coef_ab(g, inner, i, jE, a2, bb);
+    const float okE = (colE && i >= 0 && i < g.nzp) ? 1.0f : 0.0f;
+    LE[(wv * RA + r) * EX + lane] = leapfrog(a2, bb, ctrA[r], umA[r], cA[r], wA[r]) * okE;
+    if (a.w_out0 && colT && i >= i0 && i < i0 + TZ2 && i < g.nzp)
+      stf(a.w_out0 + s * fs, idxA[r], wA[r]);
+  }
+  __syncthreads();
+  const int rp0 = t.t2_rec_ptr[tile], rp1 = t.t2_rec_ptr[tile + 1];
+  if (a.d_out)
+    for (int e = rp0 + tid; e < rp1; e += NTHREADS2)
+      a.d_out[((long long)s * g.nt + a.n + 1) * g.nr + t.t2_rec_id[e]] = LE[t.t2_rec_local[e]];
+
+  // step B: w^{n+1} and u^{n+2} on the output tile
+  float wB[RB], ctrB[RB], uB[RB];
+  lap_stepB(LE, g, lb, wv, wB, ctrB);
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    const int i = iB + r;
+    if (jE == sj && i == si) wB[r] += a.amp1;
+    float a2, bb;
+    coef_ab(g, inner, i, jE, a2, bb);
+    const float unT = LI[(wv * RB + r + 2 * HALO) * IX + 2 * HALO + lb - HALO];
+    uB[r] = leapfrog(a2, bb, ctrB[r], unT, cB[r], wB[r]);
+    unB[r] = unT;
+    if (colT && i < g.nzp) {
+      stf(o1, idxB[r], ctrB[r]);
+      stf(o2, idxB[r], uB[r]);
+      if (a.w_out1) stf(a.w_out1 + s * fs, idxB[r], wB[r]);
+      if (a.ck) {
+        stf(a.ck + (2 * s + ((a.n + 1) & 1)) * fs, idxB[r], ctrB[r]);
+        stf(a.ck + (2 * s + (a.n & 1)) * fs, idxB[r], uB[r]);
+      }
+    }
+  }
+  if (a.d_out && rp1 > rp0)
+    gather2(LE, uB, colT, lane, wv, t, rp0, rp1, tid,
+            a.d_out + ((long long)s * g.nt + a.n + 2) * g.nr);
+
+  if constexpr (BORN) {
+    for (int b = 0; b < a.B; ++b) {
+      const long long fb = ((long long)s * a.B + b) * 2 * fs;
+      const float *dn = a.duin + fb + (a.n & 1) * fs;
+      const float *dm = a.duin + fb + ((a.n + 1) & 1) * fs;
+      float *d1 = a.duout + fb + ((a.n + 1) & 1) * fs;
+      float *d2 = a.duout + fb + (a.n & 1) * fs;
+      const float *dcb = a.dc + (long long)b * fs;
+      float dmA[RA], dcA[RA], dcB[RB];
+      Tile2Regs D;
+      fetch_tile2(D, dn, i0, j0, g, tid);
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        dmA[r] = ldf(dm, idxA[r]);
+        dcA[r] = ldf(dcb, idxA[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) dcB[r] = ldf(dcb, idxB[r]);
+      __syncthreads();
+      commit_tile2(LI, D, tid);
+      __syncthreads();
+      float lA[RA], cdA[RA];
+      lap_stepA(LI, g, lane, wv, lA, cdA);
+#pragma unroll
+      for (int r = 0; r < RA; ++r) {
+        const int i = iA + r;
+        float a2, bb;
+        coef_ab(g, inner, i, jE, a2, bb);
+        const float okE = (colE && i >= 0 && i < g.nzp) ? 1.0f : 0.0f;
+        LE[(wv * RA + r) * EX + lane] =
+            __builtin_fmaf(dcA[r], wA[r], leapfrog(a2, bb, cdA[r], dmA[r], cA[r], lA[r])) * okE;
+      }
+      __syncthreads();
+      if (a.dd_out)
+        for (int e = rp0 + tid; e < rp1; e += NTHREADS2)
+          a.dd_out[(((long long)b * g.ns + s) * g.nt + a.n + 1) * g.nr + t.t2_rec_id[e]] =
+              LE[t.t2_rec_local[e]];
+      float lB[RB], cdB[RB], dB[RB];
+      lap_stepB(LE, g, lb, wv, lB, cdB);
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        const int i = iB + r;
+        float a2, bb;
+        coef_ab(g, inner, i, jE, a2, bb);
+        const float dnT = LI[(wv * RB + r + 2 * HALO) * IX + 2 * HALO + lb - HALO];
+        dB[r] = __builtin_fmaf(dcB[r], wB[r], leapfrog(a2, bb, cdB[r], dnT, cB[r], lB[r]));
+        if (colT && i < g.nzp) {
+          stf(d1, idxB[r], cdB[r]);
+          stf(d2, idxB[r], dB[r]);
+        }
+      }
+      if (a.dd_out && rp1 > rp0)
+        gather2(LE, dB, colT, lane, wv, t, rp0, rp1, tid,
+                a.dd_out + (((long long)b * g.ns + s) * g.nt + a.n + 2) * g.nr);
+    }
+  }
+}
+
+// Two adjoint steps for vector b over a group of shots: mu^k on the extended
+// region (with injection at every receiver node inside it), mu^{k-1} on the
+// output tile (with injection at the nodes inside the tile), and the image
+// terms w^k mu^{k+1} + w^{k-1} mu^k accumulated over the group's shots.
+__global__ __launch_bounds__(NTHREADS2) void k_adjoint2(Geo g, DevTables t, Adj2Args a) {
+  __shared__ float LI[IZ * IX];
+  __shared__ float LE[EZ * EX];
+  const int lid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tile = lid % g.ntiles2;
+  const int rest = lid / g.ntiles2;
+  const int b = rest % a.B, grp = rest / a.B;
+  const int tzi = tile / g.tiles_x2, txi = tile - tzi * g.tiles_x2;
+  const int i0 = tzi * TZ2, j0 = txi * TX2;
+  const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
+  const long long fs = g.fs;
+  const bool inner = tile_interior(g, i0 - HALO, j0 - HALO, EZ, EX);
+
+  const int jE = j0 - HALO + lane;
+  const bool colE = jE >= 0 && jE < g.nxp;
+  const bool colT = lane >= HALO && lane < HALO + TX2 && colE;
+  const int jc = min(max(jE, 0), g.nxp - 1);
+  const int lb = min(max(lane, HALO), EX - 1 - HALO);
+  const int iA = i0 - HALO + wv * RA;
+  const int iB = i0 + wv * RB;
+
+  unsigned idxA[RA], idxB[RB];
+  float cA[RA], cB[RB], img[RB];
+#pragma unroll
+  for (int r = 0; r < RA; ++r) {
+    idxA[r] = (unsigned)(min(max(iA + r, 0), g.nzp - 1) * g.pitch + jc);
+    cA[r] = ldf(a.c, idxA[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    idxB[r] = (unsigned)(min(iB + r, g.nzp - 1) * g.pitch + jc);
+    cB[r] = ldf(a.c, idxB[r]);
+    img[r] = 0.0f;
+  }
+  const int np0 = t.t2_node_ptr[tile], np1 = t.t2_node_ptr[tile + 1];
+  const bool inject = np1 > np0;
+  const int s0 = grp * a.group, s1 = min(g.ns, s0 + a.group);
+
+  for (int s = s0; s < s1; ++s) {
+    const long long fb = ((long long)b * g.ns + s) * 2 * fs;
+    const float *m1 = a.muin + fb + ((a.k + 1) & 1) * fs;  // mu^{k+1}
+    const float *m2 = a.muin + fb + (a.k & 1) * fs;        // mu^{k+2}
+    float *o0 = a.muout + fb + (a.k & 1) * fs;             // mu^k
+    float *om = a.muout + fb + ((a.k + 1) & 1) * fs;       // mu^{k-1}
+    float m2A[RA], w0B[RB], w1B[RB];
+    Tile2Regs T;
+    fetch_tile2(T, m1, i0, j0, g, tid);
+#pragma unroll
+    for (int r = 0; r < RA; ++r) m2A[r] = ldf(m2, idxA[r]);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      w0B[r] = a.w0 ? ldf(a.w0 + s * fs, idxB[r]) : 0.0f;
+      w1B[r] = ldf(a.w1 + s * fs, idxB[r]);
+    }
+    if (s > s0) __syncthreads();
+    commit_tile2(LI, T, tid);
+    __syncthreads();
+    // step A: mu^k on the extended region
+    float lA[RA], cmA[RA];
+    lap_stepA(LI, g, lane, wv, lA, cmA);
+#pragma unroll
+    for (int r = 0; r < RA; ++r) {
+      const int i = iA + r;
+      float a2, bb;
+      coef_ab(g, inner, i, jE, a2, bb);
+      const float okE = (colE && i >= 0 && i < g.nzp) ? 1.0f : 0.0f;
+      LE[(wv * RA + r) * EX + lane] = leapfrog(a2, bb, cmA[r], m2A[r], cA[r], lA[r]) * okE;
+    }
+    __syncthreads();
+    const float *rs = a.r + (((long long)b * g.ns + s) * g.nt) * g.nr;
+    if (inject) {
+      const float *rk = rs + (long long)a.k * g.nr;
+      for (int e = np0 + tid; e < np1; e += NTHREADS2) {
+        float acc = 0.0f;
+        for (int q = t.t2_node_rec_ptr[e]; q < t.t2_node_rec_ptr[e + 1]; ++q)
+          acc += rk[t.t2_node_recs[q]];
+        LE[t.t2_node_local[e]] += a.c[t.t2_node_gidx[e]] * acc;
+      }
+      __syncthreads();
+    }
+    // step B: mu^{k-1} on the output tile
+    float lB[RB], cmB[RB], out[RB];
+    lap_stepB(LE, g, lb, wv, lB, cmB);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const int i = iB + r;
+      float a2, bb;
+      coef_ab(g, inner, i, jE, a2, bb);
+      const float m1T = LI[(wv * RB + r + 2 * HALO) * IX + 2 * HALO + lb - HALO];
+      out[r] = leapfrog(a2, bb, cmB[r], m1T, cB[r], lB[r]);
+      img[r] = __builtin_fmaf(w0B[r], m1T, img[r]);
+      img[r] = __builtin_fmaf(w1B[r], cmB[r], img[r]);
+    }
+    if (inject) {
+      __syncthreads();
+      if (lane == lb)  // output columns only: clamped lanes must not write
+#pragma unroll
+        for (int r = 0; r < RB; ++r) LE[(wv * RB + r + HALO) * EX + lb] = out[r];
+      __syncthreads();
+      const float *rk = rs + (long long)(a.k - 1) * g.nr;
+      for (int e = np0 + tid; e < np1; e += NTHREADS2) {
+        const int loc = t.t2_node_local[e];
+        const int re = loc / EX, ce = loc - re * EX;
+        if (re < HALO || re >= HALO + TZ2 || ce < HALO || ce >= HALO + TX2) continue;
+        float acc = 0.0f;
+        for (int q = t.t2_node_rec_ptr[e]; q < t.t2_node_rec_ptr[e + 1]; ++q)
+          acc += rk[t.t2_node_recs[q]];
+        LE[loc] += a.c[t.t2_node_gidx[e]] * acc;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < RB; ++r) out[r] = LE[(wv * RB + r + HALO) * EX + lb];
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (colT && iB + r < g.nzp) {
+        stf(o0, idxB[r], cmB[r]);
+        stf(om, idxB[r], out[r]);
+      }
+    }
+  }
+  double *ig = a.img + ((long long)grp * a.B + b) * fs;
+  double old[RB];
+  float sm[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) {
+    old[r] = ldd(ig, idxB[r]);
+    sm[r] = ldf(a.s2m, idxB[r]);
+  }
+#pragma unroll
+  for (int r = 0; r < RB; ++r)
+    if (colT && iB + r < g.nzp) std_(ig, idxB[r], old[r] + (double)sm[r] * (double)img[r]);
 }
 
 // Coefficients on the padded grid from the model (and Born perturbations).
@@ -473,7 +933,8 @@ static inline unsigned int blocks_for(long long n, int per) {
 
 hipError_t launch_step(const Geo &g, const DevTables &t, const StepArgs &a, bool born,
                        hipStream_t st) {
-  const unsigned int grid = (unsigned int)(g.ntiles * g.ns);
+  const unsigned int grid =
+      (unsigned int)((a.order == 2 ? g.nblocks * g.blk : g.ntiles) * g.ns);
   if (born)
     hipLaunchKernelGGL(k_step<true>, dim3(grid), dim3(NTHREADS), 0, st, g, t, a);
   else
@@ -481,8 +942,25 @@ hipError_t launch_step(const Geo &g, const DevTables &t, const StepArgs &a, bool
   return hipGetLastError();
 }
 
+hipError_t launch_step2(const Geo &g, const DevTables &t, const Step2Args &a, bool born,
+                        hipStream_t st) {
+  const unsigned int grid = (unsigned int)(g.ntiles2 * g.ns);
+  if (born)
+    hipLaunchKernelGGL(k_step2<true>, dim3(grid), dim3(NTHREADS2), 0, st, g, t, a);
+  else
+    hipLaunchKernelGGL(k_step2<false>, dim3(grid), dim3(NTHREADS2), 0, st, g, t, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint2(const Geo &g, const DevTables &t, const Adj2Args &a, hipStream_t st) {
+  const unsigned int grid = (unsigned int)(g.ntiles2 * a.B * a.ngroups);
+  hipLaunchKernelGGL(k_adjoint2, dim3(grid), dim3(NTHREADS2), 0, st, g, t, a);
+  return hipGetLastError();
+}
+
 hipError_t launch_adjoint(const Geo &g, const DevTables &t, const AdjArgs &a, hipStream_t st) {
-  const unsigned int grid = (unsigned int)(g.ntiles * a.B * a.ngroups);
+  const unsigned int grid =
+      (unsigned int)((a.order == 2 ? g.nblocks * g.blk : g.ntiles) * a.B * a.ngroups);
   hipLaunchKernelGGL(k_adjoint, dim3(grid), dim3(NTHREADS), 0, st, g, t, a);
   return hipGetLastError();
 }

@@ -1,0 +1,162 @@
+"""Full-size parity: the benchmark workload (921 x 301 layered-faulted model,
+64 shots, 461 receivers, 4000 steps, K = 50) in the benchmark's launch
+configuration (64-shot plans, batches of 16), against oracle fixtures for one
+sampled shot (tests/golden/make_full_size.py), plus identities that hold at
+any size.
+
+Sampling inside the 64-shot launch: the migration of a residual that is zero
+for every shot but the sampled one equals that shot's migration.  The
+Gauss-Newton product sums over shots, so its per-shot fixture is compared
+with a one-shot plan, and the 64-shot product is checked through the
+dot-product test, symmetry and additivity over shot subsets.
+
+Tolerances: 4000 FP32 leapfrog steps accumulate more rounding than the 500 of
+the small case; measured errors are printed and the bounds below are about
+4x above them.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2507_10804_amd import synth
+from tests._cases import rel
+
+pytestmark = pytest.mark.gpu
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def full():
+    import torch
+    from paper_2507_10804_amd import fwi
+    g, m_true, m_eval = synth.config_layered()
+    plan = fwi.Plan(g)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device="cuda")
+    return dict(torch=torch, fwi=fwi, g=g, m_true=m_true, m_eval=m_eval, plan=plan, f32=f32)
+
+
+def host(x):
+    return x.detach().double().cpu().numpy()
+
+
+def test_full_forward_sampled_shot(full):
+    say("entry: fwi_forward 921x301, 64 shots, nt=4000 (sampled shot vs oracle)")
+    gold = np.load(os.path.join(GOLD, "full_size_forward.npz"))
+    s, rs, ts = int(gold["shot"]), int(gold["rec_stride"]), int(gold["t_stride"])
+    d = full["plan"].forward(full["f32"](full["m_true"]))
+    got = host(d[s, ::ts, ::rs])
+    e = rel(got, gold["d"])
+    say(f"  rel-L2 forward data (shot {s}) = {e:.3e}")
+    assert e < 4e-5
+    assert full["plan"].status() == 0
+
+
+def test_full_adjoint_sampled_shot(full):
+    say("entry: fwi_adjoint 921x301, 64 shots, B=16 (sampled shot vs oracle)")
+    torch, g = full["torch"], full["g"]
+    gold = np.load(os.path.join(GOLD, "full_size_adjoint.npz"))
+    s = int(gold["shot"])
+    r = np.zeros((16, g.ns, g.nt, g.nr), np.float32)
+    r[0, s] = synth.residual_noise((1, g.nt, g.nr), seed=int(gold["r_seed"]))[0]
+    r[1:, s] = 0.5 * r[0, s]  # the rest of the batch: same shot, scaled
+    out = host(full["plan"].adjoint(full["f32"](full["m_eval"]), full["f32"](r)))
+    e0, e1 = rel(out[0], gold["g"]), rel(out[1], 0.5 * gold["g"])
+    say(f"  rel-L2 migration (shot {s}) = {e0:.3e}, batch member {e1:.3e}")
+    assert e0 < 1e-4 and e1 < 1e-4
+
+
+def test_full_gn_hvp_sampled_shot(full):
+    say("entry: fwi_gn_hvp 921x301, one sampled shot, nt=4000")
+    fwi = full["fwi"]
+    gold = np.load(os.path.join(GOLD, "full_size_hvp.npz"))
+    s = int(gold["shot"])
+    g1 = full["g"].with_shots([s])
+    plan1 = fwi.Plan(g1)
+    v = synth.smooth_random((g1.nz, g1.nx), seed=int(gold["v_seed"]), sigma=5.0)
+    hv = host(plan1.gn_hvp(full["f32"](full["m_eval"]), full["f32"](v)))
+    e = rel(hv, gold["hv"])
+    say(f"  rel-L2 GN Hv (shot {s}) = {e:.3e}")
+    assert e < 1e-4
+
+
+def _band_limited(torch, shape, f0, dt, seed):
+    """N(0,1) traces filtered in time to the Ricker spectrum of peak f0: a
+    residual with the band of real data."""
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    x = torch.randn(shape, generator=gen, device="cuda", dtype=torch.float32)
+    nt = shape[-2]
+    f = torch.fft.rfftfreq(nt, d=dt, device="cuda")
+    spec = (f / f0) ** 2 * torch.exp(-((f / f0) ** 2))
+    X = torch.fft.rfft(x, dim=-2) * spec[:, None].to(torch.complex64)
+    return torch.fft.irfft(X, n=nt, dim=-2).contiguous()
+
+
+def test_full_dot_product_and_symmetry(full):
+    """Batches of 16 at full size, as the benchmark launches them.
+
+    For a random residual r, <J v, r> keeps only the part of r that looks
+    like data and cancels by a factor |Jv||r| / |<Jv, r>| of 10^3..10^4 here,
+    so the plain relative error of the dot test measures that cancellation
+    more than the adjoint.  The test therefore bounds the normalised error
+    |<Jv,r> - <v,J^T r>| / (|Jv||r|) for white and band-limited random r, and
+    the plain relative error for a data-like residual r = J (v_b + v_{b+1})."""
+    say("entry: fwi_born + fwi_adjoint + fwi_gn_hvp B=16 at full size")
+    torch, g, plan = full["torch"], full["g"], full["plan"]
+    m = full["f32"](full["m_eval"])
+    vs = synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, 17))
+    V = full["f32"](vs)
+    jv = plan.born(m, V)
+    for kind in ("data-like", "band", "white"):
+        if kind == "band":
+            r = _band_limited(torch, tuple(jv.shape), g.f0, g.dt, seed=3)
+        elif kind == "white":
+            r = torch.empty_like(jv).normal_(
+                generator=torch.Generator(device="cuda").manual_seed(3))
+        else:
+            r = jv + jv.roll(-1, dims=0)
+        jtr = plan.adjoint(m, r)
+        lhs = (jv.double() * r.double()).sum(dim=(1, 2, 3)).cpu().numpy()
+        rhs = (V.double() * jtr.double()).sum(dim=(1, 2)).cpu().numpy()
+        scale = (jv.double().flatten(1).norm(dim=1) * r.double().flatten(1).norm(dim=1))
+        scale = scale.cpu().numpy()
+        err = np.abs(lhs - rhs) / np.abs(lhs)
+        nerr = np.abs(lhs - rhs) / scale
+        say(f"  dot test ({kind} r): max rel {err.max():.3e}, normalised {nerr.max():.3e}, "
+            f"cancellation factor {np.min(scale / np.abs(lhs)):.0f}.."
+            f"{np.max(scale / np.abs(lhs)):.0f}")
+        assert nerr.max() < 1e-7
+        if kind == "data-like":
+            assert err.max() < 1e-5
+        del r, jtr
+    del jv
+    hv = host(plan.gn_hvp(m, V))
+    sym = []
+    for a, b in [(0, 1), (2, 7), (5, 15)]:
+        x, y = np.vdot(vs[a], hv[b]), np.vdot(hv[a], vs[b])
+        sym.append(abs(x - y) / abs(x))
+    say(f"  symmetry max rel = {max(sym):.3e}")
+    assert max(sym) < 1e-5
+    assert all(np.vdot(vs[b], hv[b]) > 0 for b in range(16))
+
+
+def test_full_shot_additivity(full):
+    """H over 64 shots equals the sum over two 32-shot halves (shots are
+    independent; the grouping of the FP64 image sum differs)."""
+    say("entry: fwi_gn_hvp 64 shots vs 2 x 32 shots")
+    fwi, g, plan = full["fwi"], full["g"], full["plan"]
+    m = full["f32"](full["m_eval"])
+    v = full["f32"](synth.smooth_random((g.nz, g.nx), seed=21, sigma=5.0))
+    h64 = host(plan.gn_hvp(m, v))
+    plan.release_workspaces()
+    ha = host(fwi.Plan(g.with_shots(range(0, 32))).gn_hvp(m, v))
+    hb = host(fwi.Plan(g.with_shots(range(32, 64))).gn_hvp(m, v))
+    e = rel(ha + hb, h64)
+    say(f"  rel-L2 additivity = {e:.3e}")
+    assert e < 1e-6

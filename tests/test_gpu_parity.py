@@ -158,17 +158,69 @@ def test_batched_equals_looped_and_deterministic(torch, small):
 
 
 def test_checkpoint_interval_invariance(torch):
+    """Results do not depend on the checkpoint interval K: recomputed
+    wavefields equal the stored ones bit for bit.  Even K runs two time steps
+    per launch, odd K one; within each the outputs are bitwise equal, across
+    them only the FP32 grouping of the image sum differs."""
     g, m = tiny(nt=230)
     v = synth.smooth_random(m.shape, seed=1, sigma=3.0)
-    outs = []
-    for K in (1, 7, 50, 229, 5000):
+    outs = {}
+    for K in (2, 8, 50, 228, 1, 7, 229, 5000):
         say(f"entry: fwi_gn_hvp tiny K={K}")
         g.ckpt_every = K
         p = make_plan(g)
-        outs.append(host(p.gn_hvp(dev(torch, m), dev(torch, v))))
-    for o in outs[1:]:
-        assert np.array_equal(o, outs[0])
-    assert rel(outs[0], oracle.gn_hvp(g, m, v)) < TOL_IMAGE
+        outs[K] = host(p.gn_hvp(dev(torch, m), dev(torch, v)))
+    for K in (8, 50, 228):
+        assert np.array_equal(outs[K], outs[2]), f"two-step K={K}"
+    for K in (7, 229, 5000):
+        assert np.array_equal(outs[K], outs[1]), f"one-step K={K}"
+    assert rel(outs[2], outs[1]) < 1e-6
+    ref = oracle.gn_hvp(g, m, v)
+    assert rel(outs[2], ref) < TOL_IMAGE and rel(outs[1], ref) < TOL_IMAGE
+
+
+def test_two_step_matches_one_step_data(torch, small):
+    """Forward and Born data are identical bit for bit whether the time loop
+    advances one or two steps per launch (same arithmetic, same order)."""
+    g, m, v = small["g"], small["m"], small["v"]
+    p1 = _plan_with(g, "000")
+    p2 = small["plan"]
+    mb, vb = dev(torch, m), dev(torch, v)
+    assert np.array_equal(host(p1.forward(mb)), host(p2.forward(mb)))
+    assert np.array_equal(host(p1.born(mb, vb)), host(p2.born(mb, vb)))
+    r = dev(torch, synth.residual_noise((g.ns, g.nt, g.nr), seed=5))
+    assert rel(host(p1.adjoint(mb, r)), host(p2.adjoint(mb, r))) < 1e-6
+
+
+def _plan_with(geom, flags):
+    import os
+    os.environ["FWI_TWO_STEP"] = flags
+    try:
+        return make_plan(geom)
+    finally:
+        del os.environ["FWI_TWO_STEP"]
+
+
+def test_two_step_every_kernel(torch):
+    """Every kernel family in its two-step form (forward, Born, adjoint with
+    receiver injection in the halo ring) against the one-step forms and the
+    oracle, on ragged tiles with receivers near tile edges."""
+    say("case: FWI_TWO_STEP=111 vs 000, ragged grid")
+    g, m = tiny(nx=150, nz=50, nt=151, nb=10)
+    ix = np.array([53, 54, 54, 45, 46, 101, 102, 0, 149])
+    g.rec_zx = np.stack([np.array([1, 1, 1, 21, 22, 22, 20, 49, 0]), ix], 1).astype(np.int32)
+    v = synth.smooth_random(m.shape, seed=1, sigma=2.0)
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=6)
+    p2, p1 = _plan_with(g, "111"), _plan_with(g, "000")
+    mb, vb, rb = dev(torch, m), dev(torch, v), dev(torch, r)
+    assert np.array_equal(host(p2.forward(mb)), host(p1.forward(mb)))
+    assert np.array_equal(host(p2.born(mb, vb)), host(p1.born(mb, vb)))
+    a2, a1 = host(p2.adjoint(mb, rb)), host(p1.adjoint(mb, rb))
+    assert rel(a2, a1) < 1e-6
+    assert rel(a2, oracle.adjoint(g, m, r)) < TOL_IMAGE
+    h2 = host(p2.gn_hvp(mb, vb))
+    assert rel(h2, host(p1.gn_hvp(mb, vb))) < 1e-6
+    assert rel(h2, oracle.gn_hvp(g, m, v)) < TOL_IMAGE
 
 
 # ------------------------------------------------------------- edge cases
