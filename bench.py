@@ -32,9 +32,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "GN Hessian-vector products/s + Gpt-updates/s (%HBM peak); p50/p99 Hv latency"
-KERNEL_NAMES = {0: "k_step<false>", 1: "k_step<true>", 2: "k_adjoint"}
+KERNEL_NAMES = (0, 1, 2)  # forward, forward+Born, adjoint (see fwi.Plan.kernel_name)
 KERNEL_SRC = os.path.join(ROOT, "paper_2507_10804_amd", "csrc", "fwi_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_c2_gn_hvp.md")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_kernels_921x301_64shots_traffic.md")
 
 
 def log(*a):
@@ -289,11 +289,14 @@ def main():
         nseg = (g.nt - 1 + plan.K - 1) // plan.K
         alg = algorithmic_bytes(g, B, nseg, plan.K)
         kern = {}
-        for kind, name in KERNEL_NAMES.items():
+        for kind in KERNEL_NAMES:
+            name = plan.kernel_name(kind)
             ms, n = plan.profile_read(kind)
             n_step = n / args.steps
             per_launch = alg[kind] / n_step if n_step else 0.0
-            kern[name] = {"launches_per_step": n_step, "avg_us": 1e3 * ms / max(n, 1),
+            kern[name] = {"kind": ["forward", "forward+Born", "adjoint"][kind],
+                          "steps_per_launch": plan.kernel_steps(kind),
+                          "launches_per_step": n_step, "avg_us": 1e3 * ms / max(n, 1),
                           "total_ms_per_step": ms / args.steps,
                           "alg_bytes_per_launch": per_launch,
                           "achieved_gbs": per_launch / (1e-3 * ms / max(n, 1)) / 1e9 if n else 0}

@@ -188,6 +188,9 @@ enum {
   FWI_KERNEL_ADJOINT = 2     /* adjoint + imaging time step */
 };
 int fwi_profile_enable(fwi_plan *p, int enable);
+/* Time steps one launch of kernel `kind` advances under this plan: 2 where
+ * the temporally blocked form is used (it needs an even K), else 1. */
+int fwi_kernel_steps(const fwi_plan *p, int kind, int32_t *steps);
 int fwi_profile_read(fwi_plan *p, int kind, double *total_ms, int64_t *launches);
 int fwi_profile_reset(fwi_plan *p);
 

@@ -65,8 +65,9 @@ struct fwi_plan {
          off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0, off_order = 0;
   size_t off2[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // two-step tables
   // advance two time steps per launch (needs K even), per kernel family;
-  // defaults from measurement: only the Born kernel gains
-  bool ts_fwd = false, ts_born = true, ts_adj = false;
+  // defaults from measurement: the Born and adjoint kernels gain, the plain
+  // forward does not
+  bool ts_fwd = false, ts_born = true, ts_adj = true;
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
@@ -772,6 +773,16 @@ int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, vo
 int fwi_profile_enable(fwi_plan *p, int enable) {
   if (!p) return fail(FWI_EINVAL, "null plan");
   p->profiling = enable != 0;
+  return FWI_OK;
+}
+
+int fwi_kernel_steps(const fwi_plan *p, int kind, int32_t *steps) {
+  if (!p || !steps) return fail(FWI_EINVAL, "null argument");
+  if (kind < 0 || kind > 2) return fail(FWI_EINVAL, "unknown kernel kind");
+  const bool two = kind == FWI_KERNEL_STEP ? p->ts_fwd
+                   : kind == FWI_KERNEL_STEP_BORN ? p->ts_born
+                                                  : p->ts_adj;
+  *steps = two ? 2 : 1;
   return FWI_OK;
 }
 

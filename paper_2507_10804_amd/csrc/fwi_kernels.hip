@@ -669,7 +669,7 @@ __global__ __launch_bounds__(NTHREADS2) void k_step2(Geo g, DevTables t, Step2Ar
 // region (with injection at every receiver node inside it), mu^{k-1} on the
 // output tile (with injection at the nodes inside the tile), and the image
 // terms w^k mu^{k+1} + w^{k-1} mu^k accumulated over the group's shots.
-__global__ __launch_bounds__(NTHREADS2) void k_adjoint2(Geo g, DevTables t, Adj2Args a) {
+__global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint2(Geo g, DevTables t, Adj2Args a) {
   __shared__ float LI[IZ * IX];
   __shared__ float LE[EZ * EX];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);

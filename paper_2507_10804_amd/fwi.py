@@ -23,7 +23,7 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_plan_bind", "fwi_workspace_size", "fwi_plan_dims", "fwi_forward", "fwi_born",
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
            "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset",
-           "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit"]
+           "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit", "fwi_kernel_steps"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -78,6 +78,7 @@ def load_library(path: str = LIB_PATH):
             "fwi_forward_keep": ([P, P, P, P, Z, P], I),
             "fwi_adjoint_resume": ([P, P, I, P, P, Z, P], I),
             "fwi_misfit": ([P, P, P, P, P, Z, P], I),
+            "fwi_kernel_steps": ([P, I, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -291,6 +292,18 @@ class Plan:
         n = ctypes.c_int64()
         _check(self.lib.fwi_profile_read(self._h, int(kind), ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+    def kernel_steps(self, kind):
+        """Time steps one launch of kernel `kind` advances (1 or 2)."""
+        n = ctypes.c_int32()
+        _check(self.lib.fwi_kernel_steps(self._h, int(kind), ctypes.byref(n)))
+        return n.value
+
+    def kernel_name(self, kind):
+        two = self.kernel_steps(kind) == 2
+        return {KERNEL_STEP: "k_step2<false>" if two else "k_step<false>",
+                KERNEL_STEP_BORN: "k_step2<true>" if two else "k_step<true>",
+                KERNEL_ADJOINT: "k_adjoint2" if two else "k_adjoint"}[kind]
 
     def status(self):
         """Synchronise, return and clear the device status bits."""
