@@ -68,6 +68,8 @@ struct fwi_plan {
   // defaults from measurement: the Born and adjoint kernels gain, the plain
   // forward does not
   bool ts_fwd = false, ts_born = true, ts_adj = true;
+  int adj_pair = 2;  // vectors per two-step adjoint workgroup (1..4)
+  int adj_nb(int B) const { return std::min(adj_pair, B); }
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
@@ -98,7 +100,8 @@ int adjoint_group(const fwi_plan *p, int B) {
   if (p->adj_group_override > 0) return std::min(p->adj_group_override, p->geo.ns);
   // Enough workgroups to fill 256 CUs several times over, and as many shots
   // per workgroup as that allows (fewer partial-image updates).
-  const long long base = (long long)p->geo.ntiles * B;
+  const int nbg = p->ts_adj ? (B + p->adj_nb(B) - 1) / p->adj_nb(B) : B;
+  const long long base = (long long)p->geo.ntiles * nbg;
   int group = 1;
   while (group < 16 && group * 2 <= p->geo.ns &&
          base * ((p->geo.ns + group * 2 - 1) / (group * 2)) >= 4096)
@@ -316,6 +319,7 @@ int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
       a.B = B;
       a.group = L.group;
       a.ngroups = L.G;
+      a.nb = p->adj_nb(B);
       for (; k - 1 >= n0; k -= 2, mcur ^= 1) {
         a.k = k;
         a.muin = mu + mcur * ms;
@@ -582,6 +586,7 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
     }
   }
   if (p->K % 2) p->ts_fwd = p->ts_born = p->ts_adj = false;
+  if (const char *e = std::getenv("FWI_ADJ_PAIR")) p->adj_pair = std::max(1, std::min(4, std::atoi(e)));
   *out = p;
   return FWI_OK;
 }

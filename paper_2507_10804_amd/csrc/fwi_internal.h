@@ -109,6 +109,7 @@ struct Adj2Args {
   int B;
   int group;
   int ngroups;
+  int nb;              // vectors per workgroup (share the loads of w), <= 4
 };
 
 // Arguments of one forward / forward+Born time step.

@@ -665,17 +665,23 @@ __global__ __launch_bounds__(NTHREADS2) void k_step2(Geo g, DevTables t, Step2Ar
   }
 }
 
-// Two adjoint steps for vector b over a group of shots: mu^k on the extended
-// region (with injection at every receiver node inside it), mu^{k-1} on the
-// output tile (with injection at the nodes inside the tile), and the image
-// terms w^k mu^{k+1} + w^{k-1} mu^k accumulated over the group's shots.
+// Two adjoint steps for a.nb vectors over a group of shots: mu^k on the
+// extended region (with injection at every receiver node inside it), mu^{k-1}
+// on the output tile (with injection at the nodes inside the tile), and the
+// image terms w^k mu^{k+1} + w^{k-1} mu^k accumulated over the group's shots.
+// The forward levels w^k, w^{k-1} of a shot are loaded once for all the
+// workgroup's vectors; each vector's image accumulates in dynamic LDS, in
+// entries private to the thread that owns the output point.
 __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_adjoint2(Geo g, DevTables t, Adj2Args a) {
+  extern __shared__ float LIMG[];  // [nb][TZ2][EX]
   __shared__ float LI[IZ * IX];
   __shared__ float LE[EZ * EX];
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % g.ntiles2;
   const int rest = lid / g.ntiles2;
-  const int b = rest % a.B, grp = rest / a.B;
+  const int nbg = (a.B + a.nb - 1) / a.nb;
+  const int b0 = (rest % nbg) * a.nb, grp = rest / nbg;
+  const int nbv = min(a.nb, a.B - b0);  // vectors of this workgroup
   const int tzi = tile / g.tiles_x2, txi = tile - tzi * g.tiles_x2;
   const int i0 = tzi * TZ2, j0 = txi * TX2;
   const int tid = threadIdx.x, lane = tid % TX, wv = tid / TX;
@@ -691,7 +697,7 @@ __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8)
   const int iB = i0 + wv * RB;
 
   unsigned idxA[RA], idxB[RB];
-  float cA[RA], cB[RB], img[RB];
+  float cA[RA], cB[RB];
 #pragma unroll
   for (int r = 0; r < RA; ++r) {
     idxA[r] = (unsigned)(min(max(iA + r, 0), g.nzp - 1) * g.pitch + jc);
@@ -701,29 +707,35 @@ __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8)
   for (int r = 0; r < RB; ++r) {
     idxB[r] = (unsigned)(min(iB + r, g.nzp - 1) * g.pitch + jc);
     cB[r] = ldf(a.c, idxB[r]);
-    img[r] = 0.0f;
   }
+  for (int q = 0; q < nbv; ++q)
+#pragma unroll
+    for (int r = 0; r < RB; ++r) LIMG[(q * TZ2 + wv * RB + r) * EX + lane] = 0.0f;
   const int np0 = t.t2_node_ptr[tile], np1 = t.t2_node_ptr[tile + 1];
   const bool inject = np1 > np0;
   const int s0 = grp * a.group, s1 = min(g.ns, s0 + a.group);
 
   for (int s = s0; s < s1; ++s) {
+   float w0B[RB], w1B[RB];
+#pragma unroll
+   for (int r = 0; r < RB; ++r) {
+     w0B[r] = a.w0 ? ldf(a.w0 + s * fs, idxB[r]) : 0.0f;
+     w1B[r] = ldf(a.w1 + s * fs, idxB[r]);
+   }
+#pragma unroll 1
+   for (int q = 0; q < nbv; ++q) {
+    const int b = b0 + q;
     const long long fb = ((long long)b * g.ns + s) * 2 * fs;
     const float *m1 = a.muin + fb + ((a.k + 1) & 1) * fs;  // mu^{k+1}
     const float *m2 = a.muin + fb + (a.k & 1) * fs;        // mu^{k+2}
     float *o0 = a.muout + fb + (a.k & 1) * fs;             // mu^k
     float *om = a.muout + fb + ((a.k + 1) & 1) * fs;       // mu^{k-1}
-    float m2A[RA], w0B[RB], w1B[RB];
+    float m2A[RA];
     Tile2Regs T;
     fetch_tile2(T, m1, i0, j0, g, tid);
 #pragma unroll
     for (int r = 0; r < RA; ++r) m2A[r] = ldf(m2, idxA[r]);
-#pragma unroll
-    for (int r = 0; r < RB; ++r) {
-      w0B[r] = a.w0 ? ldf(a.w0 + s * fs, idxB[r]) : 0.0f;
-      w1B[r] = ldf(a.w1 + s * fs, idxB[r]);
-    }
-    if (s > s0) __syncthreads();
+    if (s > s0 || q > 0) __syncthreads();
     commit_tile2(LI, T, tid);
     __syncthreads();
     // step A: mu^k on the extended region
@@ -759,8 +771,8 @@ __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8)
       coef_ab(g, inner, i, jE, a2, bb);
       const float m1T = LI[(wv * RB + r + 2 * HALO) * IX + 2 * HALO + lb - HALO];
       out[r] = leapfrog(a2, bb, cmB[r], m1T, cB[r], lB[r]);
-      img[r] = __builtin_fmaf(w0B[r], m1T, img[r]);
-      img[r] = __builtin_fmaf(w1B[r], cmB[r], img[r]);
+      float *acc = LIMG + (q * TZ2 + wv * RB + r) * EX + lane;
+      *acc = __builtin_fmaf(w1B[r], cmB[r], __builtin_fmaf(w0B[r], m1T, *acc));
     }
     if (inject) {
       __syncthreads();
@@ -789,18 +801,22 @@ __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8)
         stf(om, idxB[r], out[r]);
       }
     }
+   }
   }
-  double *ig = a.img + ((long long)grp * a.B + b) * fs;
-  double old[RB];
   float sm[RB];
 #pragma unroll
-  for (int r = 0; r < RB; ++r) {
-    old[r] = ldd(ig, idxB[r]);
-    sm[r] = ldf(a.s2m, idxB[r]);
-  }
+  for (int r = 0; r < RB; ++r) sm[r] = ldf(a.s2m, idxB[r]);
+  for (int q = 0; q < nbv; ++q) {
+    double *ig = a.img + ((long long)grp * a.B + b0 + q) * fs;
+    double old[RB];
 #pragma unroll
-  for (int r = 0; r < RB; ++r)
-    if (colT && iB + r < g.nzp) std_(ig, idxB[r], old[r] + (double)sm[r] * (double)img[r]);
+    for (int r = 0; r < RB; ++r) old[r] = ldd(ig, idxB[r]);
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      const float im = LIMG[(q * TZ2 + wv * RB + r) * EX + lane];
+      if (colT && iB + r < g.nzp) std_(ig, idxB[r], old[r] + (double)sm[r] * (double)im);
+    }
+  }
 }
 
 // Coefficients on the padded grid from the model (and Born perturbations).
@@ -953,8 +969,9 @@ hipError_t launch_step2(const Geo &g, const DevTables &t, const Step2Args &a, bo
 }
 
 hipError_t launch_adjoint2(const Geo &g, const DevTables &t, const Adj2Args &a, hipStream_t st) {
-  const unsigned int grid = (unsigned int)(g.ntiles2 * a.B * a.ngroups);
-  hipLaunchKernelGGL(k_adjoint2, dim3(grid), dim3(NTHREADS2), 0, st, g, t, a);
+  const unsigned int grid = (unsigned int)(g.ntiles2 * ((a.B + a.nb - 1) / a.nb) * a.ngroups);
+  const size_t lds = (size_t)a.nb * TZ2 * EX * sizeof(float);
+  hipLaunchKernelGGL(k_adjoint2, dim3(grid), dim3(NTHREADS2), lds, st, g, t, a);
   return hipGetLastError();
 }
 
