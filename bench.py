@@ -166,6 +166,150 @@ def serve_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def _kernel_table(plan, steps, alg=None):
+    kern = {}
+    for kind in KERNEL_NAMES:
+        ms, n = plan.profile_read(kind)
+        if not n:
+            continue
+        name = plan.kernel_name(kind)
+        kern[name] = {"steps_per_launch": plan.kernel_steps(kind),
+                      "launches_per_step": n / steps, "avg_us": 1e3 * ms / n,
+                      "total_ms_per_step": ms / steps}
+        if alg is not None:
+            per = alg[kind] / (n / steps)
+            kern[name]["alg_bytes_per_launch"] = per
+            kern[name]["achieved_gbs"] = per / (1e-3 * ms / n) / 1e9
+    return kern
+
+
+def probing_bench(args):
+    """Batched probing row: 64 Gauss-Newton products per launch at the
+    smoothed layered model (921x301, 64 shots, 4000 steps) on impulse combs
+    (a delta every 40 cells, offsets without replacement) and smoothed +-1
+    Rademacher probes, the whole call captured once in a HIP graph and
+    replayed; the same calls eagerly for comparison."""
+    import torch
+    from paper_2507_10804_amd import fwi, probing, synth
+
+    g, m_true, m_eval = synth.config_layered(nt=args.nt)
+    B = 64
+    combs = synth.impulse_combs(g.nz, g.nx, count=B, spacing=40, seed=100)
+    rad = synth.rademacher_smoothed(g.nz, g.nx, seeds=range(200, 200 + B), sigma=5.0)
+    dev = torch.device("cuda:0")
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    me = f32(m_eval)
+    t0 = time.perf_counter()
+    sess = probing.ProbeSession(plan, me, batch=B, use_graph=True)
+    t_capture = time.perf_counter() - t0
+    log(f"probing: graph captured in {t_capture:.1f} s (includes one eager warm-up call)")
+    out = {"metric": "GN Hessian-vector products/s, batched probing (64 per launch)",
+           "unit": "Hv/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"layered-faulted 921x301, {g.ns} shots, nt={g.nt}, "
+                                  "64 impulse combs + 64 smoothed Rademacher probes per "
+                                  "launch, HIP-graph replay", "batch": B},
+           "graph_capture_s": t_capture}
+    for mode in ("graph", "eager"):
+        times = []
+        for name, V in (("combs", combs), ("rademacher", rad)):
+            Vd = f32(V)
+            torch.cuda.synchronize()
+            plan.profile(mode == "eager")
+            plan.profile_reset()
+            t1 = time.perf_counter()
+            if mode == "graph":
+                sess.run(Vd)
+            else:
+                plan.gn_hvp(me, Vd, out=sess.hv)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t1)
+            log(f"{mode} {name}: {times[-1]:.2f} s")
+            if mode == "eager" and name == "rademacher":
+                nseg = (g.nt - 1 + plan.K - 1) // plan.K
+                alg = algorithmic_bytes_hvp(g, B, nseg)
+                out["kernels"] = _kernel_table(plan, 1, alg)
+            plan.profile(False)
+        out[mode] = {"s_per_launch": float(np.mean(times)), "hv_per_s": B / float(np.mean(times))}
+    out["value"] = out["graph"]["hv_per_s"]
+    k = max(out["kernels"], key=lambda n: out["kernels"][n]["total_ms_per_step"])
+    kk = out["kernels"][k]
+    out["roofline"] = {"bound": "hbm", "kernel": k, "achieved": kk["achieved_gbs"],
+                       "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": kk["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                       "avg_launch_us": kk["avg_us"]}
+    print(json.dumps(out), flush=True)
+
+
+def algorithmic_bytes_hvp(g, B, nseg):
+    """Algorithmic bytes of one B-vector Hessian-vector call alone (forward
+    + Born, recompute, adjoint), per kernel kind (see algorithmic_bytes)."""
+    nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
+    Np = nzp * nxp
+    ns, nr, nt = g.ns, g.nr, g.nt
+    rec = (nt - 1) * (4 * Np * (3 * ns + 1) + 4 * ns * Np)
+    born = ((nt - 1) * (4 * Np * (3 * ns + 1) + 4 * Np * B * (3 * ns + 1) + 4 * B * ns * nr)
+            + (nseg - 1) * 8 * ns * Np)
+    adj = nt * (12 * Np * B * ns + 4 * B * ns * nr) + (nt - 1) * (4 * Np * ns + 8 * Np + 16 * Np * B)
+    return {0: rec, 1: born, 2: adj}
+
+
+def autograd_bench(args):
+    """Differentiation row: misfit and gradient, migration, and one
+    Gauss-Newton product through the torch.autograd.Function on the
+    921x301 / 64-shot / 4000-step workload, against the direct ABI calls."""
+    import torch
+    from paper_2507_10804_amd import autograd as ag
+    from paper_2507_10804_amd import fwi, synth
+
+    g, m_true, m_eval = synth.config_layered(nt=args.nt)
+    dev = torch.device("cuda:0")
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    mt, me = f32(m_true), f32(m_eval)
+    v = f32(synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0))
+    dobs = plan.forward(mt)
+    torch.cuda.synchronize()
+
+    def timeit(fn, reps=args.steps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    def ag_grad():
+        m = me.clone().requires_grad_(True)
+        d = ag.forward(m, plan)
+        (0.5 * ((d - dobs) ** 2).sum()).backward()
+        return m.grad
+
+    def ag_misfit():
+        m = me.clone().requires_grad_(True)
+        ag.misfit(m, dobs, plan).backward()
+        return m.grad
+
+    res = {
+        "direct misfit_grad": timeit(lambda: plan.misfit_grad(me, dobs)),
+        "autograd Misfit + backward": timeit(ag_misfit),
+        "autograd FwiForward + backward (checkpoint resume)": timeit(ag_grad),
+        "direct gn_hvp B=1": timeit(lambda: plan.gn_hvp(me, v)),
+        "autograd jvp then vjp": timeit(lambda: ag.gn_hvp_autograd(me, v, plan)),
+    }
+    for k, t in res.items():
+        log(f"{k}: {t * 1e3:.0f} ms")
+    out = {"metric": "autograd layer: seconds per gradient / Gauss-Newton product vs direct",
+           "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"layered-faulted 921x301, {g.ns} shots, nt={g.nt}, K=50"},
+           "seconds": res,
+           "value": res["autograd FwiForward + backward (checkpoint resume)"]}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,7 +325,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
-    ap.add_argument("--mode", choices=["hvp", "serve"], default="hvp")
+    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd"], default="hvp")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -189,6 +333,12 @@ def main():
     args = ap.parse_args()
     if args.mode == "serve":
         serve_bench(args)
+        return
+    if args.mode == "probing":
+        probing_bench(args)
+        return
+    if args.mode == "autograd":
+        autograd_bench(args)
         return
     if args.calibrate_copy:
         calibrate_copy()

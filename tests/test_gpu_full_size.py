@@ -160,3 +160,37 @@ def test_full_shot_additivity(full):
     e = rel(ha + hb, h64)
     say(f"  rel-L2 additivity = {e:.3e}")
     assert e < 1e-6
+
+
+def test_full_autograd(full):
+    """The differentiation layer at full size: the backward of FwiForward for
+    a residual on the sampled shot equals that shot's oracle migration, and
+    the misfit gradient agrees with a central difference of the misfit
+    (h = 1e-3 relative; FP32 data bound the agreement to ~1e-3)."""
+    from paper_2507_10804_amd import autograd as ag
+    say("entry: autograd FwiForward / Misfit at 921x301, 64 shots, nt=4000")
+    torch, g, plan, f32 = full["torch"], full["g"], full["plan"], full["f32"]
+    plan.release_workspaces()
+    gold = np.load(os.path.join(GOLD, "full_size_adjoint.npz"))
+    s = int(gold["shot"])
+    r = np.zeros((g.ns, g.nt, g.nr), np.float32)
+    r[s] = synth.residual_noise((1, g.nt, g.nr), seed=int(gold["r_seed"]))[0]
+    m = f32(full["m_eval"]).requires_grad_(True)
+    d = ag.forward(m, plan)
+    (gm,) = torch.autograd.grad(d, m, grad_outputs=f32(r))
+    e = rel(host(gm), gold["g"])
+    say(f"  rel-L2 autograd backward (shot {s}) = {e:.3e}")
+    assert e < 1e-4
+    del d, gm
+    dobs = plan.forward(f32(full["m_true"]))
+    m0 = full["m_eval"]
+    v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
+    mm = f32(m0).requires_grad_(True)
+    ag.misfit(mm, dobs, plan).backward()
+    dirv = float(np.vdot(host(mm.grad), v))
+    h = 1e-3 * np.abs(m0).max() / np.abs(v).max()
+    fp = float(plan.misfit(f32(m0 + h * v), dobs))
+    fm = float(plan.misfit(f32(m0 - h * v), dobs))
+    fd = (fp - fm) / (2 * h)
+    say(f"  FD {fd:.6e} vs <grad, v> {dirv:.6e} (rel {abs(fd - dirv) / abs(dirv):.2e})")
+    assert fd == pytest.approx(dirv, rel=2e-3)
