@@ -155,7 +155,8 @@ def serve_bench(args):
             t0 = time.monotonic()
             recs, tw, t1 = wl.run_closed_loop(srv, be, banks, chains=32, rate=50.0,
                                               requests_per_chain=args.requests_per_chain,
-                                              seed=args.seed, warmup_s=args.serve_warmup)
+                                              seed=args.seed, warmup_s=args.serve_warmup,
+                                              log=log)
         torch.cuda.synchronize()
         res = wl.summarize(recs, tw, t1)
         res["wall_s"] = t1 - t0

@@ -57,10 +57,27 @@ def load_datasets(backend, keys=tuple(GRIDS), nt_override=None):
     return banks
 
 
+class Progress:
+    """Completed-request counter that reports every `every` completions."""
+
+    def __init__(self, every=32, log=None):
+        self.every, self.log = every, log
+        self.n = 0
+        self.lock = threading.Lock()
+        self.t0 = time.monotonic()
+
+    def tick(self):
+        with self.lock:
+            self.n += 1
+            if self.log and self.n % self.every == 0:
+                self.log(f"  {self.n} requests done, {time.monotonic() - self.t0:.0f} s")
+
+
 class Chain:
     """One closed-loop client: think, submit, wait, repeat."""
 
-    def __init__(self, idx, server, backend, banks, mean_think, keys, seed=0, probe_every=10):
+    def __init__(self, idx, server, backend, banks, mean_think, keys, seed=0, probe_every=10,
+                 progress=None):
         self.idx = idx
         self.server = server
         self.backend = backend
@@ -71,6 +88,7 @@ class Chain:
         self.probe_every = probe_every
         self.records = []
         self.stop = False
+        self.progress = progress
 
     def make_request(self, n):
         import torch
@@ -109,14 +127,18 @@ class Chain:
             r = fut.request
             self.records.append((r.kind, r.nvec, r.t_submit, r.t_start, r.t_end, r.batch, ok,
                                  r.dataset))
+            if self.progress:
+                self.progress.tick()
 
 
 def run_closed_loop(server, backend, banks, chains=32, rate=50.0, requests_per_chain=20,
-                    keys=tuple(GRIDS), seed=0, warmup_s=0.0):
+                    keys=tuple(GRIDS), seed=0, warmup_s=0.0, log=None):
     """32 chains with exponential think times (aggregate offered rate `rate`
     when service were instantaneous); returns per-request records."""
     mean_think = chains / rate
-    cs = [Chain(i, server, backend, banks, mean_think, keys, seed) for i in range(chains)]
+    prog = Progress(log=log)
+    cs = [Chain(i, server, backend, banks, mean_think, keys, seed, progress=prog)
+          for i in range(chains)]
     th = [threading.Thread(target=c.run, args=(requests_per_chain,), daemon=True) for c in cs]
     t0 = time.monotonic()
     for t in th:
