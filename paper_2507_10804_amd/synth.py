@@ -226,6 +226,66 @@ def impulse_combs(nz, nx, count=64, spacing=40, seed=100) -> np.ndarray:
     return out
 
 
+@dataclass(frozen=True)
+class PsfGrid:
+    """Sample points of the point-spread-function method (Section 3.2) on a
+    model grid of nz x nx cells: centres at rows oz + p*sz (p < nzc) and
+    columns ox + q*sx (q < nxc), PSF k = p*nxc + q, each PSF kept on the
+    window of half-width ``half`` cells around its centre.  The probing
+    vectors are ``stride``^2 combs; comb (p % stride)*stride + q % stride holds
+    the deltas of every centre with those residues, so deltas of one comb are
+    stride*sz rows and stride*sx columns apart."""
+
+    nz: int
+    nx: int
+    oz: int
+    ox: int
+    sz: int
+    sx: int
+    nzc: int
+    nxc: int
+    half: int
+    stride: int = 2
+
+    @property
+    def r(self) -> int:
+        return self.nzc * self.nxc
+
+    @property
+    def width(self) -> int:
+        return 2 * self.half + 1
+
+    @property
+    def ncombs(self) -> int:
+        return self.stride * self.stride
+
+    def centres(self) -> np.ndarray:
+        """(r, 2) int array of (iz, ix)."""
+        p, q = np.meshgrid(np.arange(self.nzc), np.arange(self.nxc), indexing="ij")
+        return np.stack([self.oz + p.ravel() * self.sz, self.ox + q.ravel() * self.sx], axis=1)
+
+
+def psf_grid(nz, nx, spacing=32, half=None, stride=2) -> PsfGrid:
+    """Centres every `spacing` cells, the first half a spacing in from the
+    edge, as many as fit; PSF windows as wide as the comb spacing allows
+    (2*half + 1 <= stride*spacing, so windows of one comb never overlap)."""
+    o = spacing // 2
+    nzc = (nz - 1 - o) // spacing + 1
+    nxc = (nx - 1 - o) // spacing + 1
+    if half is None:
+        half = (stride * spacing - 1) // 2
+    return PsfGrid(nz, nx, o, o, spacing, spacing, nzc, nxc, half, stride)
+
+
+def psf_combs(g: PsfGrid) -> np.ndarray:
+    """The g.ncombs probing vectors: unit deltas at the centres of each comb."""
+    out = np.zeros((g.ncombs, g.nz, g.nx), dtype=np.float64)
+    for k, (iz, ix) in enumerate(g.centres()):
+        p, q = divmod(k, g.nxc)
+        out[(p % g.stride) * g.stride + q % g.stride, iz, ix] = 1.0
+    return out
+
+
 def rademacher_smoothed(nz, nx, seeds, sigma=5.0) -> np.ndarray:
     out = []
     for s in seeds:
