@@ -243,6 +243,104 @@ def probing_bench(args):
     print(json.dumps(out), flush=True)
 
 
+FP32_VALU_PEAK_TFLOPS = 157.3
+
+
+def psf_algorithmic_flops(pg):
+    """FLOPs of one symbol-row apply of one vector by its definition: for
+    every PSF k, every output y with w_k(y) > 0 and every tap d, one
+    multiply-add (2 FLOPs).  The tent support of centre j on an axis of n
+    cells spans the open interval to its neighbours, or to the edge for the
+    first and last centre."""
+
+    def support(n, first, s, count):
+        if count == 1:
+            return [n]
+        c = [first + j * s for j in range(count)]
+        out = [c[1]]
+        out += [c[j + 1] - c[j - 1] - 1 for j in range(1, count - 1)]
+        out.append(n - 1 - c[-2])
+        return out
+
+    sz = support(pg.nz, pg.oz, pg.sz, pg.nzc)
+    sx = support(pg.nx, pg.ox, pg.sx, pg.nxc)
+    return 2.0 * sum(sz) * sum(sx) * pg.width * pg.width
+
+
+def psf_bench(args):
+    """PSF approximation row (Sections 3.2, 3.5) on the 921x301 / 64-shot /
+    4000-step workload at the smoothed model: 4 comb Hessian products (one
+    batched call) give the PSFs of a 9 x 29 lattice (spacing 32, windows
+    63 x 63), extracted on the device; the approximation is then applied to
+    batches of smooth vectors and compared with true products."""
+    import torch
+    from oracle import psf as P
+    from paper_2507_10804_amd import fwi, synth
+    from paper_2507_10804_amd import psf as gpsf
+
+    g, m_true, m_eval = synth.config_layered(nt=args.nt)
+    pg = synth.psf_grid(g.nz, g.nx)
+    dev = torch.device("cuda:0")
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    me = f32(m_eval)
+    B = args.batch
+    V = f32(synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, B + 1)))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    op = gpsf.PsfOperator(plan, me, pg)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    log(f"psf: {pg.r} PSFs from {pg.ncombs} comb products in {t_build:.1f} s")
+    out_buf = torch.empty_like(V)
+    for _ in range(args.warmup + 1):
+        op(V, out=out_buf)
+    torch.cuda.synchronize()
+    reps = max(5, args.steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for _ in range(reps):
+        op(V, out=out_buf)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1]) / reps
+    log(f"psf: apply of {B} vectors {ms:.3f} ms")
+    flops = psf_algorithmic_flops(pg) * B
+    achieved = flops / (ms * 1e-3) / 1e12
+    # quality on the true operator (information, not parity): four smooth vectors
+    hv = plan.gn_hvp(me, V[:4])
+    approx = op(V[:4])
+    q = [float((approx[i] - hv[i]).norm() / hv[i].norm()) for i in range(4)]
+    torch.cuda.synchronize()
+    plan.release_workspaces()
+    out = {"metric": "PSF-approximate H_d v applies/s", "unit": "applies/s",
+           "value": B / (ms * 1e-3), "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"layered-faulted 921x301 at the smoothed model, {g.ns} shots, "
+                                  f"nt={g.nt}; PSF lattice {pg.nzc}x{pg.nxc} (spacing {pg.sz}, "
+                                  f"window {pg.width}x{pg.width}) from {pg.ncombs} comb products; "
+                                  f"apply to {B} smooth vectors per call", "batch": B,
+                      "psfs": pg.r, "window": pg.width},
+           "build_s": t_build,
+           "psf_rel_error_vs_true_hv": q,
+           "roofline": {"bound": "alu", "kernel": "k_psf_rows", "achieved": achieved,
+                        "peak": FP32_VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": achieved / FP32_VALU_PEAK_TFLOPS, "traffic": None,
+                        "alg_flops_per_launch": flops, "avg_launch_us": ms * 1e3}}
+    if not args.no_cpu_baseline:
+        vh = V[0].double().cpu().numpy()
+        ph = op.psf.double().cpu().numpy()
+        t1 = time.perf_counter()
+        P.apply_rows(pg, ph, vh)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "applies/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one vector through the FP64 oracle's symbol-row "
+                                         f"apply on the full grid, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def algorithmic_bytes_hvp(g, B, nseg):
     """Algorithmic bytes of one B-vector Hessian-vector call alone (forward
     + Born, recompute, adjoint), per kernel kind (see algorithmic_bytes)."""
@@ -326,7 +424,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
-    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd"], default="hvp")
+    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd", "psf"], default="hvp")
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -338,6 +436,8 @@ def main():
     if args.mode == "probing":
         probing_bench(args)
         return
+    if args.mode == "psf":
+        return psf_bench(args)
     if args.mode == "autograd":
         autograd_bench(args)
         return

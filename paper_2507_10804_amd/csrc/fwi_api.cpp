@@ -53,6 +53,8 @@ size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 }  // namespace
 
+int fwi::set_error(int code, const std::string &msg) { return fail(code, msg); }
+
 struct fwi_plan {
   Geo geo{};
   int K = 1, nseg = 1;

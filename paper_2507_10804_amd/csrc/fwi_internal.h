@@ -5,7 +5,13 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <string>
+
 namespace fwi {
+
+// Records `msg` as the calling thread's last error (fwi_last_error) and
+// returns `code`.
+int set_error(int code, const std::string &msg);
 
 // Tile of one workgroup: 64 columns (one wavefront wide) by TZ rows; each of
 // the NWAVE wavefronts owns RZ consecutive rows of every column.

@@ -1,4 +1,5 @@
-"""Thin ctypes binding of the C ABI in ``include/fwi.h``.
+"""Thin ctypes binding of the C ABI in ``include/fwi.h`` (and the PSF entry
+points of ``include/fwi_psf.h``, wrapped in :mod:`.psf`).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``libfwi_mi355x.so``.  PyTorch supplies device memory (plan block,
@@ -23,7 +24,8 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_plan_bind", "fwi_workspace_size", "fwi_plan_dims", "fwi_forward", "fwi_born",
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
            "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset",
-           "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit", "fwi_kernel_steps"]
+           "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit", "fwi_kernel_steps",
+           "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -79,6 +81,9 @@ def load_library(path: str = LIB_PATH):
             "fwi_adjoint_resume": ([P, P, I, P, P, Z, P], I),
             "fwi_misfit": ([P, P, P, P, P, Z, P], I),
             "fwi_kernel_steps": ([P, I, P], I),
+            "fwi_psf_check": ([P], I),
+            "fwi_psf_extract": ([P, P, P, P], I),
+            "fwi_psf_apply": ([P, P, P, I, P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)

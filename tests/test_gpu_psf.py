@@ -1,0 +1,145 @@
+"""PSF approximation on the GPU against the FP64 oracle (oracle/psf.py).
+
+* extraction is a gather: bit-exact against the oracle on the same FP32 data;
+* the symbol-row apply sums up to 4 * 65^2 FP32 products per output: rel-L2
+  below 1e-5 per vector (FP32 accumulation of ~1.6e4 terms of random sign
+  gives ~1e-6);
+* shapes cover several 32 x 32 sub-tiles per cell, boundary strips wider
+  than a sub-tile, ragged edges, one-centre lattices, half-widths 0 and 32,
+  one-cell grids and batches;
+* end to end on a small wave problem: comb Hessian products on the GPU,
+  extraction and apply against the oracle's products, extraction and apply
+  (the Hessian-product tolerance 1e-4 bounds it);
+* the benchmark's lattice on the 921 x 301 grid in the benchmark's launch
+  configuration, against the oracle's full apply.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import psf as P
+from paper_2507_10804_amd import synth
+from tests._cases import rel, tiny
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, a):
+    return torch.as_tensor(np.asarray(a, np.float32), device="cuda")
+
+
+CASES = [
+    # nz, nx, oz, ox, sz, sx, nzc, nxc, half, stride
+    (37, 45, 3, 3, 8, 8, 5, 6, 5, 2),
+    (101, 157, 35, 10, 40, 70, 2, 3, 12, 2),  # strips and cells wider than a sub-tile
+    (64, 64, 0, 0, 32, 32, 2, 2, 32, 1),       # largest half-width, centre on the edge
+    (50, 70, 49, 69, 1, 1, 1, 1, 7, 1),        # one centre in the last cell
+    (1, 1, 0, 0, 1, 1, 1, 1, 0, 1),            # one cell
+    (33, 97, 16, 5, 16, 9, 2, 11, 0, 3),       # half-width 0: pointwise weights
+    (300, 40, 7, 39, 25, 3, 12, 1, 20, 2),     # one centre column
+]
+
+
+@pytest.mark.parametrize("case", CASES)
+def test_apply_matches_oracle(case):
+    import torch
+    from paper_2507_10804_amd import psf as gpsf
+
+    g = synth.PsfGrid(*case)
+    say(f"case: fwi_psf_apply {g}")
+    rng = np.random.default_rng(sum(case))
+    psf = rng.standard_normal((g.r, g.width, g.width)).astype(np.float32)
+    B = 3
+    v = rng.standard_normal((B, g.nz, g.nx)).astype(np.float32)
+    out = gpsf.apply(g, dev(torch, psf), dev(torch, v)).double().cpu().numpy()
+    errs = []
+    for b in range(B):
+        ref = P.apply_rows(g, psf.astype(np.float64), v[b].astype(np.float64))
+        errs.append(rel(out[b], ref))
+    say(f"  rel-L2 per vector: {', '.join(f'{e:.2e}' for e in errs)}")
+    assert max(errs) < 1e-5
+    one = gpsf.apply(g, dev(torch, psf), dev(torch, v[1])).double().cpu().numpy()
+    assert np.array_equal(one, out[1])  # batching and determinism
+
+
+@pytest.mark.parametrize("case", CASES[:3])
+def test_extract_bit_exact(case):
+    import torch
+    from paper_2507_10804_amd import psf as gpsf
+
+    g = synth.PsfGrid(*case)
+    say(f"case: fwi_psf_extract {g}")
+    hv = np.random.default_rng(7).standard_normal((g.ncombs, g.nz, g.nx)).astype(np.float32)
+    got = gpsf.extract(g, dev(torch, hv)).cpu().numpy()
+    ref = P.extract(g, hv.astype(np.float64)).astype(np.float32)
+    assert np.array_equal(got, ref)
+
+
+def test_argument_errors():
+    import torch
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import psf as gpsf
+
+    g = synth.PsfGrid(*CASES[0])
+    psf = torch.zeros((g.r, g.width, g.width), device="cuda")
+    v = torch.zeros((2, g.nz, g.nx), device="cuda")
+    bad = synth.PsfGrid(37, 45, 3, 3, 8, 8, 5, 7, 5, 2)  # last centre column outside
+    with pytest.raises(fwi.FwiError):
+        gpsf.apply(bad, torch.zeros((bad.r, bad.width, bad.width), device="cuda"), v)
+    with pytest.raises(ValueError):
+        gpsf.apply(g, psf[:-1], v)
+
+
+def test_end_to_end_small_wave_problem():
+    """Comb products through fwi_gn_hvp, then extraction and apply, against
+    the oracle's comb products, extraction and apply."""
+    import torch
+    import oracle
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import psf as gpsf
+
+    geom, m = tiny(nx=64, nz=48, ns=3, nr=16, nt=260)
+    m2 = synth.smoothed_start(m, 2.0)
+    g = synth.psf_grid(geom.nz, geom.nx, spacing=16, half=7)
+    say(f"case: PsfOperator on a 64x48 wave problem, {g.r} PSFs from {g.ncombs} products")
+    plan = fwi.Plan(geom)
+    op = gpsf.PsfOperator(plan, dev(torch, m2), g)
+    combs = synth.psf_combs(g)
+    m64 = np.float32(m2).astype(np.float64)
+    hv_o = np.stack([oracle.gn_hvp(geom, m64, c) for c in combs])
+    psf_o = P.extract(g, hv_o)
+    e_psf = rel(op.psf.double().cpu().numpy(), psf_o)
+    v = synth.smooth_random((geom.nz, geom.nx), seed=3, sigma=2.0)
+    got = op(dev(torch, v)).double().cpu().numpy()
+    ref = P.apply_rows(g, psf_o, v)
+    e_apply = rel(got, ref)
+    say(f"  rel-L2 PSFs {e_psf:.2e}, apply {e_apply:.2e}")
+    assert e_psf < 1e-4 and e_apply < 1e-4
+
+
+def test_full_size_lattice():
+    import torch
+    from paper_2507_10804_amd import psf as gpsf
+
+    g = synth.psf_grid(301, 921)
+    say(f"case: fwi_psf_apply 921x301, {g.r} PSFs, half {g.half}, B=16 (vector 5 vs oracle)")
+    rng = np.random.default_rng(11)
+    psf = rng.standard_normal((g.r, g.width, g.width)).astype(np.float32)
+    v = synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, 17)).astype(np.float32)
+    out = gpsf.apply(g, dev(torch, psf), dev(torch, v))
+    got = out[5].double().cpu().numpy()
+    ref = P.apply_rows(g, psf.astype(np.float64), v[5].astype(np.float64))
+    e = rel(got, ref)
+    say(f"  rel-L2 = {e:.2e}")
+    assert e < 1e-5
+    pts = [(0, 0), (300, 920), (16, 16), (17, 47), (150, 460), (299, 1)]
+    for b in (0, 15):
+        at = P.apply_rows_at(g, psf.astype(np.float64), v[b].astype(np.float64), pts)
+        o = out[b].double().cpu().numpy()
+        assert np.allclose([o[i, j] for i, j in pts], at, rtol=1e-4, atol=1e-4 * np.abs(at).max())
