@@ -46,8 +46,9 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(g, B, nseg, K):
-    """Compulsory HBM bytes of one step (gradient + one B-vector Hv call),
+def algorithmic_bytes(g, B, nseg, K, fused=True):
+    """Compulsory HBM bytes of one step (misfit, gradient and B products at
+    one model: one fused pass, or a gradient call plus a B-vector Hv call),
     per kernel kind: every array element a launch must read or write, once.
 
     Np = padded grid points.  Per launch:
@@ -73,6 +74,9 @@ def algorithmic_bytes(g, B, nseg, K):
     def adj(b):
         return nt * (12 * Np * b * ns + 4 * b * ns * nr) + (nt - 1) * (4 * Np * ns + 8 * Np + 16 * Np * b)
 
+    if fused:
+        # one pass: forward+Born (gathering d and J v) + one recompute + adjoint(B + 1)
+        return {0: rec, 1: born + (nt - 1) * 4 * ns * nr, 2: adj(B + 1)}
     # gradient: forward (gathering d) + recompute + adjoint(B=1)
     # Hv call : forward+Born + recompute + adjoint(B)
     return {0: fwd + 2 * rec, 1: born, 2: adj(1) + adj(B)}
@@ -429,6 +433,9 @@ def main():
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--separate", action="store_true",
+                    help="time the step as fwi_misfit_grad + fwi_gn_hvp instead of the fused "
+                         "fwi_misfit_grad_hvp")
     args = ap.parse_args()
     if args.mode == "serve":
         serve_bench(args)
@@ -469,7 +476,13 @@ def main():
     ws_gb = (plan.workspace_bytes(fwi.FWI_OP_GN_HVP, B) +
              plan.workspace_bytes(fwi.FWI_OP_MISFIT_GRAD)) / 1e9
 
+    fused = not args.separate
+    if fused:
+        ws_gb = plan.workspace_bytes(fwi.FWI_OP_GRAD_HVP, B) / 1e9
+
     def step():
+        if fused:
+            return plan.misfit_grad_hvp(me, dobs, vd, out=hv)[:2]
         phi, grad = plan.misfit_grad(me, dobs)
         plan.gn_hvp(me, vd, out=hv)
         return phi, grad
@@ -491,9 +504,13 @@ def main():
     for i in range(args.steps):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(st)
-        phi, grad = plan.misfit_grad(me, dobs)
-        e1.record(st)
-        plan.gn_hvp(me, vd, out=hv)
+        if fused:
+            plan.misfit_grad_hvp(me, dobs, vd, out=hv)
+            e1.record(st)
+        else:
+            phi, grad = plan.misfit_grad(me, dobs)
+            e1.record(st)
+            plan.gn_hvp(me, vd, out=hv)
         e2.record(st)
         ev.append((e0, e1, e2))
     torch.cuda.synchronize()
@@ -504,11 +521,14 @@ def main():
         raise RuntimeError("device status flags set in the timed region")
 
     ms_step = wall * 1e3 / args.steps
+    call_lat = np.array([e[0].elapsed_time(e[2]) for e in ev])
     hv_lat = np.array([e[1].elapsed_time(e[2]) for e in ev])
     grad_lat = np.array([e[0].elapsed_time(e[1]) for e in ev])
     nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
     solve_updates = g.ns * nzp * nxp * (g.nt - 1)
-    solves = 2 + 1 + 2 * B  # gradient: fwd + adj; Hv: fwd + B Born + B adjoint
+    # credited solves (recomputes are not): fused = forward + B Born + (B + 1) adjoint;
+    # separate = gradient (forward + adjoint) + Hv (forward + B Born + B adjoint)
+    solves = 2 + 2 * B if fused else 2 + 1 + 2 * B
     gpts = solves * solve_updates / (ms_step * 1e-3) / 1e9
     out = {
         "metric": METRIC,
@@ -524,21 +544,28 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"layered-faulted 921x301 dx=10m, {g.ns} shots, {g.nr} receivers, "
-                               f"Ricker 8 Hz, nt={g.nt}, K={plan.K}: misfit gradient + "
-                               f"{B} GN Hv per step",
+                               f"Ricker 8 Hz, nt={g.nt}, K={plan.K}: misfit, gradient and "
+                               f"{B} GN Hv at one model per step"
+                               + (", one fused pass (shared forward solve and recompute)"
+                                  if fused else ", as two calls"),
+                   "call": "fwi_misfit_grad_hvp" if fused else "fwi_misfit_grad + fwi_gn_hvp",
                    "grid": [g.nz, g.nx], "padded": [nzp, nxp], "shots": g.ns,
                    "receivers": g.nr, "nt": g.nt, "batch": B, "ckpt_every": plan.K,
                    "workspace_gb": round(ws_gb, 2)},
         "gpt_updates_per_s": gpts,
         "hbm_headline_frac": gpts * 1e9 * 16 / (HBM_PEAK_GBS * 1e9),
-        "hv_call_latency_ms": {"p50": float(np.percentile(hv_lat, 50)),
-                               "p99": float(np.percentile(hv_lat, 99)), "batch": B},
-        "grad_latency_ms": float(np.median(grad_lat)),
     }
+    if fused:
+        out["call_latency_ms"] = {"p50": float(np.percentile(call_lat, 50)),
+                                  "p99": float(np.percentile(call_lat, 99)), "batch": B}
+    else:
+        out["hv_call_latency_ms"] = {"p50": float(np.percentile(hv_lat, 50)),
+                                     "p99": float(np.percentile(hv_lat, 99)), "batch": B}
+        out["grad_latency_ms"] = float(np.median(grad_lat))
 
     if not args.no_profile:
         nseg = (g.nt - 1 + plan.K - 1) // plan.K
-        alg = algorithmic_bytes(g, B, nseg, plan.K)
+        alg = algorithmic_bytes(g, B, nseg, plan.K, fused=fused)
         kern = {}
         for kind in KERNEL_NAMES:
             name = plan.kernel_name(kind)

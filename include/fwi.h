@@ -84,7 +84,8 @@ enum {
   FWI_OP_ADJOINT = 2,
   FWI_OP_MISFIT_GRAD = 3,
   FWI_OP_GN_HVP = 4,
-  FWI_OP_MISFIT = 5
+  FWI_OP_MISFIT = 5,
+  FWI_OP_GRAD_HVP = 6
 };
 
 typedef struct fwi_plan fwi_plan;
@@ -175,6 +176,18 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
  * its recomputation are shared by the whole batch. */
 int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, void *ws,
                size_t ws_bytes, void *stream);
+
+/* Misfit, gradient and B Gauss-Newton products at one model, in one pass
+ * (Section 3: a Hessian product reuses the forward wavefield of the gradient
+ * at the same model, leaving two solves per source and vector).  Outputs are
+ * those of fwi_misfit_grad (phi, g) and fwi_gn_hvp (hv) at m; one forward
+ * solve with the B Born fields records both the data and J v_b, one
+ * recompute serves the adjoint of the residual and of the B Born data
+ * together.  Results agree with the separate calls up to the grouping of the
+ * FP64 shot sums.  ws: fwi_workspace_size(FWI_OP_GRAD_HVP, B). */
+int fwi_misfit_grad_hvp(fwi_plan *p, const float *m, const float *dobs, const float *v, int B,
+                        double *phi, float *g, float *hv, void *ws, size_t ws_bytes,
+                        void *stream);
 
 /* Per-kernel timing telemetry.  While enabled, every launch of the three
  * stencil kernels is bracketed by a pair of HIP events recorded on the

@@ -29,7 +29,8 @@ hipError_t launch_copy(float *dst, const float *src, long long n, hipStream_t st
 hipError_t launch_zero_t0(float *d, int count, int nt, int nr, hipStream_t st);
 hipError_t launch_residual(float *d, const float *dobs, long long n, double *part, int nparts,
                            double scale, double *phi, hipStream_t st);
-hipError_t launch_fold(const Geo &g, const double *img, int G, int B, double scale, float *out,
+hipError_t launch_fold(const Geo &g, const double *img, int G, int Bst, int b0, int B,
+                       double scale, float *out,
                        hipStream_t st);
 hipError_t launch_check_finite(const float *p, long long n, unsigned int *status,
                                hipStream_t st);
@@ -70,8 +71,17 @@ struct fwi_plan {
   // defaults from measurement: the Born and adjoint kernels gain, the plain
   // forward does not
   bool ts_fwd = false, ts_born = true, ts_adj = true;
-  int adj_pair = 2;  // vectors per two-step adjoint workgroup (1..4)
-  int adj_nb(int B) const { return std::min(adj_pair, B); }
+  // vectors per two-step adjoint workgroup (1..4; 0 = by batch): pairs for
+  // even batches; for odd batches of 5 or more (the fused gradient + B
+  // products has B + 1 right-hand sides) fours, which leave one short group
+  // instead of a lone vector in a pair's slot (measured: B + 1 = 17 runs 7 %
+  // faster with fours than with pairs, B = 16 3 % slower)
+  int adj_pair = 0;
+  int adj_nb(int B) const {
+    if (adj_pair > 0) return std::min(adj_pair, B);
+    if (B % 2 == 0) return 2;
+    return B >= 5 ? 4 : B;
+  }
   void *dev = nullptr;
   DevTables tabs{};
   int adj_group_override = 0;
@@ -115,9 +125,12 @@ Layout layout(const fwi_plan *p, int op, int B) {
   const Geo &g = p->geo;
   const size_t F = (size_t)g.fs * sizeof(float);
   const size_t ndata = (size_t)g.ns * g.nt * g.nr * sizeof(float);
-  const bool needs_dc = op == FWI_OP_BORN || op == FWI_OP_GN_HVP;
-  const bool needs_adj = op == FWI_OP_ADJOINT || op == FWI_OP_MISFIT_GRAD || op == FWI_OP_GN_HVP;
-  const int Badj = op == FWI_OP_MISFIT_GRAD ? 1 : B;
+  const bool fused = op == FWI_OP_GRAD_HVP;
+  const bool needs_dc = op == FWI_OP_BORN || op == FWI_OP_GN_HVP || fused;
+  const bool needs_adj = op == FWI_OP_ADJOINT || op == FWI_OP_MISFIT_GRAD ||
+                         op == FWI_OP_GN_HVP || fused;
+  // adjoint right-hand sides: the residual (gradient) and/or B Born data
+  const int Badj = op == FWI_OP_MISFIT_GRAD ? 1 : fused ? B + 1 : B;
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -132,20 +145,22 @@ Layout layout(const fwi_plan *p, int op, int B) {
   const size_t usets = (p->ts_fwd || p->ts_born) ? 2 : 1;
   const size_t dsets = p->ts_born ? 2 : 1, msets = p->ts_adj ? 2 : 1;
   L.u = take(F * 2 * g.ns * usets);
-  if (needs_dc) L.du = take(F * 2 * g.ns * B * std::max(dsets, op == FWI_OP_GN_HVP ? msets : 1));
-  if (op == FWI_OP_GN_HVP) L.dd = take(ndata * B);
-  if (op == FWI_OP_MISFIT_GRAD || op == FWI_OP_MISFIT) {
-    L.dres = take(ndata);
+  // the Born fields are dead once the forward sweep is over: the adjoint
+  // fields of a Hessian product reuse their memory
+  const bool alias_mu = op == FWI_OP_GN_HVP || fused;
+  if (needs_dc)
+    L.du = take(F * 2 * g.ns *
+                std::max((size_t)B * dsets, alias_mu ? (size_t)Badj * msets : (size_t)0));
+  if (op == FWI_OP_GN_HVP || fused) L.dd = take(ndata * Badj);
+  if (op == FWI_OP_MISFIT_GRAD || op == FWI_OP_MISFIT) L.dres = take(ndata);
+  if (op == FWI_OP_MISFIT_GRAD || op == FWI_OP_MISFIT || fused)
     L.part = take(NPARTS * sizeof(double));
-  }
   if (needs_adj) {
     L.group = adjoint_group(p, Badj);
     L.G = (g.ns + L.group - 1) / L.group;
     L.ckpt = take(F * 2 * g.ns * p->nseg);
     L.wseg = take(F * g.ns * p->K);
-    // the Born fields are dead once the forward sweep is over: the adjoint
-    // fields of a Hessian product reuse their memory
-    L.mu = op == FWI_OP_GN_HVP ? L.du : take(F * 2 * g.ns * Badj * msets);
+    L.mu = alias_mu ? L.du : take(F * 2 * g.ns * Badj * msets);
     L.img = take((size_t)g.fs * sizeof(double) * L.G * Badj);
   }
   L.total = o;
@@ -649,7 +664,7 @@ int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream) {
 
 int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes) {
   if (!p || !bytes) return fail(FWI_EINVAL, "null argument");
-  if (op < FWI_OP_FORWARD || op > FWI_OP_MISFIT) return fail(FWI_EINVAL, "unknown op");
+  if (op < FWI_OP_FORWARD || op > FWI_OP_GRAD_HVP) return fail(FWI_EINVAL, "unknown op");
   if (batch < 1 || batch > 4096) return fail(FWI_EINVAL, "batch must be in [1, 4096]");
   *bytes = layout(p, op, batch).total;
   return FWI_OK;
@@ -693,7 +708,7 @@ int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *gout,
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
   if (int rc = forward_sweep(p, L, ws, 1, false, nullptr, nullptr, true, st)) return rc;
   if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
-  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 1.0, gout, st));
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, 1.0, gout, st));
   HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
   return FWI_OK;
 }
@@ -720,7 +735,7 @@ int fwi_adjoint_resume(fwi_plan *p, const float *r, int B, float *gout, void *ws
   const Layout L = layout(p, FWI_OP_ADJOINT, B);
   const Geo &g = p->geo;
   if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
-  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 1.0, gout, st));
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, 1.0, gout, st));
   HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
   return FWI_OK;
 }
@@ -755,7 +770,7 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
   HIP_TRY(launch_residual(dres, dobs, (long long)g.ns * g.nt * g.nr, at<double>(ws, L.part),
                           NPARTS, 0.5 * p->inv_noise_var, phi, st));
   if (int rc = reverse_sweep(p, L, ws, 1, dres, st)) return rc;
-  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, 1, p->inv_noise_var, gout, st));
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, 1, 0, 1, p->inv_noise_var, gout, st));
   HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, p->tabs.status, st));
   return FWI_OK;
 }
@@ -772,7 +787,30 @@ int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, vo
   HIP_TRY(launch_zero_t0(dd, B * g.ns, g.nt, g.nr, st));
   if (int rc = forward_sweep(p, L, ws, B, true, nullptr, dd, true, st)) return rc;
   if (int rc = reverse_sweep(p, L, ws, B, dd, st)) return rc;
-  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, p->inv_noise_var, hv, st));
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, p->inv_noise_var, hv, st));
+  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  return FWI_OK;
+}
+
+int fwi_misfit_grad_hvp(fwi_plan *p, const float *m, const float *dobs, const float *v, int B,
+                        double *phi, float *gout, float *hv, void *ws, size_t ws_bytes,
+                        void *stream) {
+  if (int rc = check_call(p, FWI_OP_GRAD_HVP, B, ws, ws_bytes)) return rc;
+  if (!m || !dobs || !v || !phi || !gout || !hv) return fail(FWI_EINVAL, "null array");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const Layout L = layout(p, FWI_OP_GRAD_HVP, B);
+  const Geo &g = p->geo;
+  const long long nd = (long long)g.ns * g.nt * g.nr;
+  float *dd = at<float>(ws, L.dd);  // [B+1][ns][nt][nr]: d - dobs, then J v_b
+  if (int rc = prologue(p, L, ws, m, v, B, true, true, st)) return rc;
+  HIP_TRY(launch_zero_t0(dd, (B + 1) * g.ns, g.nt, g.nr, st));
+  if (int rc = forward_sweep(p, L, ws, B, true, dd, dd + nd, true, st)) return rc;
+  HIP_TRY(launch_residual(dd, dobs, nd, at<double>(ws, L.part), NPARTS, 0.5 * p->inv_noise_var,
+                          phi, st));
+  if (int rc = reverse_sweep(p, L, ws, B + 1, dd, st)) return rc;
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B + 1, 0, 1, p->inv_noise_var, gout, st));
+  HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B + 1, 1, B, p->inv_noise_var, hv, st));
+  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, p->tabs.status, st));
   HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
   return FWI_OK;
 }

@@ -910,8 +910,9 @@ __global__ __launch_bounds__(256) void k_phi(const double *__restrict__ part, in
 
 // P^T and the sum over shot groups: out[b][iz][ix] = scale * sum of the
 // partial images over every padded cell that copies model cell (iz, ix).
-__global__ void k_fold(Geo g, const double *__restrict__ img, int G, int B, double scale,
-                       float *__restrict__ out) {
+// out[b] = scale * P^T sum_groups img[group][b0 + b], images [G][Bst][fs].
+__global__ void k_fold(Geo g, const double *__restrict__ img, int G, int Bst, int b0, int B,
+                       double scale, float *__restrict__ out) {
   const long long nm = (long long)g.nz * g.nx;
   const long long stride = (long long)gridDim.x * blockDim.x;
   for (long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x; q < nm * B; q += stride) {
@@ -922,7 +923,7 @@ __global__ void k_fold(Geo g, const double *__restrict__ img, int G, int B, doub
   const int ja = ix == 0 ? 0 : ix + g.nb, je = ix == g.nx - 1 ? g.nxp - 1 : ix + g.nb;
   double acc = 0.0;
   for (int gg = 0; gg < G; ++gg) {
-    const double *ig = img + ((long long)gg * B + b) * g.fs;
+    const double *ig = img + ((long long)gg * Bst + b0 + b) * g.fs;
     for (int i = ia; i <= ie; ++i)
       for (int j = ja; j <= je; ++j) acc += ig[(long long)i * g.pitch + j];
   }
@@ -1020,11 +1021,11 @@ hipError_t launch_residual(float *d, const float *dobs, long long n, double *par
   return hipGetLastError();
 }
 
-hipError_t launch_fold(const Geo &g, const double *img, int G, int B, double scale, float *out,
-                       hipStream_t st) {
+hipError_t launch_fold(const Geo &g, const double *img, int G, int Bst, int b0, int B,
+                       double scale, float *out, hipStream_t st) {
   const long long n = (long long)g.nz * g.nx * B;
-  hipLaunchKernelGGL(k_fold, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, img, G, B, scale,
-                     out);
+  hipLaunchKernelGGL(k_fold, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, img, G, Bst, b0, B,
+                     scale, out);
   return hipGetLastError();
 }
 

@@ -17,7 +17,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfwi_mi355x.so")
 
-FWI_OP_FORWARD, FWI_OP_BORN, FWI_OP_ADJOINT, FWI_OP_MISFIT_GRAD, FWI_OP_GN_HVP, FWI_OP_MISFIT = range(6)
+(FWI_OP_FORWARD, FWI_OP_BORN, FWI_OP_ADJOINT, FWI_OP_MISFIT_GRAD, FWI_OP_GN_HVP, FWI_OP_MISFIT,
+ FWI_OP_GRAD_HVP) = range(7)
 STATUS_BAD_MODEL, STATUS_CFL, STATUS_NONFINITE = 1, 2, 4
 
 EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_device_bytes",
@@ -25,7 +26,7 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
            "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset",
            "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit", "fwi_kernel_steps",
-           "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply"]
+           "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply", "fwi_misfit_grad_hvp"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -81,6 +82,7 @@ def load_library(path: str = LIB_PATH):
             "fwi_adjoint_resume": ([P, P, I, P, P, Z, P], I),
             "fwi_misfit": ([P, P, P, P, P, Z, P], I),
             "fwi_kernel_steps": ([P, I, P], I),
+            "fwi_misfit_grad_hvp": ([P, P, P, P, I, P, P, P, P, Z, P], I),
             "fwi_psf_check": ([P], I),
             "fwi_psf_extract": ([P, P, P, P], I),
             "fwi_psf_apply": ([P, P, P, I, P, P], I),
@@ -283,6 +285,27 @@ class Plan:
         _check(self.lib.fwi_gn_hvp(self._h, self._p(m), self._p(v), B, self._p(hv),
                                    self._p(ws), ws.numel(), self._stream()))
         return hv[0] if single else hv
+
+    def misfit_grad_hvp(self, m, dobs, v, out=None, ws=None):
+        """(Phi, grad, H v) at one model in one fused pass (shared forward
+        solve and recompute); v is [nz][nx] or [B][nz][nx]."""
+        g = self.geom
+        m = self._in(m, (g.nz, g.nx), "m")
+        dobs = self._in(dobs, (g.ns, g.nt, g.nr), "dobs")
+        v = self._in(v, (g.nz, g.nx), "v")
+        single = v.dim() == 2
+        v = v.reshape(-1, g.nz, g.nx)
+        B = v.shape[0]
+        t = self.torch
+        phi = t.empty((), dtype=t.float64, device=self.device)
+        grad = t.empty((g.nz, g.nx), dtype=t.float32, device=self.device)
+        hv = out if out is not None else t.empty((B, g.nz, g.nx), dtype=t.float32,
+                                                 device=self.device)
+        ws = self.workspace(FWI_OP_GRAD_HVP, B) if ws is None else ws
+        _check(self.lib.fwi_misfit_grad_hvp(self._h, self._p(m), self._p(dobs), self._p(v), B,
+                                            self._p(phi), self._p(grad), self._p(hv),
+                                            self._p(ws), ws.numel(), self._stream()))
+        return phi, grad, (hv[0] if single else hv)
 
     def profile(self, enable=True):
         """Bracket every stencil-kernel launch with HIP events (telemetry)."""

@@ -162,6 +162,31 @@ def test_full_shot_additivity(full):
     assert e < 1e-6
 
 
+def test_full_fused_grad_hvp(full):
+    """The benchmark's call: misfit, gradient and 16 products in one pass at
+    full size, against the separate calls in the same launch configuration."""
+    say("entry: fwi_misfit_grad_hvp B=16 at full size vs fwi_misfit_grad + fwi_gn_hvp")
+    torch, g, plan, f32 = full["torch"], full["g"], full["plan"], full["f32"]
+    plan.release_workspaces()
+    m = f32(full["m_eval"])
+    dobs = plan.forward(f32(full["m_true"]))
+    V = f32(synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, 17)))
+    phi, grad, hv = plan.misfit_grad_hvp(m, dobs, V)
+    hv = host(hv)
+    grad = host(grad)
+    phi = float(phi)
+    plan.release_workspaces()
+    phi_s, grad_s = plan.misfit_grad(m, dobs)
+    eg = rel(grad, host(grad_s))
+    del grad_s
+    plan.release_workspaces()
+    eh = rel(hv, host(plan.gn_hvp(m, V)))
+    say(f"  Phi {phi:.6e} vs {float(phi_s):.6e}; gradient {eg:.2e}; H v {eh:.2e}")
+    assert phi == float(phi_s)
+    assert eg < 1e-6 and eh < 1e-6
+    plan.release_workspaces()
+
+
 def test_full_autograd(full):
     """The differentiation layer at full size: the backward of FwiForward for
     a residual on the sampled shot equals that shot's oracle migration, and

@@ -157,6 +157,27 @@ def test_batched_equals_looped_and_deterministic(torch, small):
         assert rel(hb[i], host(p.gn_hvp(mb, dev(torch, vs[i])))) < 1e-6
 
 
+def test_fused_grad_hvp_matches_separate_calls(torch, small):
+    """One pass for the misfit, the gradient and B products at one model
+    equals the separate calls: the data are the same bit for bit (so is Phi);
+    the images differ only in the grouping of the FP64 shot sums."""
+    say("entry: fwi_misfit_grad_hvp B=3 vs fwi_misfit_grad + fwi_gn_hvp")
+    g, m = small["g"], small["m"]
+    p = small["plan"]
+    mb, dobs = dev(torch, m), dev(torch, small["dobs"])
+    vs = synth.smooth_random_batch(g.nz, g.nx, seeds=[21, 22, 23])
+    phi, grad, hv = p.misfit_grad_hvp(mb, dobs, dev(torch, vs))
+    phi_s, grad_s = p.misfit_grad(mb, dobs)
+    hv_s = p.gn_hvp(mb, dev(torch, vs))
+    assert float(phi) == float(phi_s)
+    eg, eh = rel(host(grad), host(grad_s)), rel(host(hv), host(hv_s))
+    say(f"  fused vs separate: gradient {eg:.2e}, H v {eh:.2e}")
+    assert eg < 1e-6 and eh < 1e-6
+    ref = oracle.gn_hvp(g, m, vs[1])
+    assert rel(host(hv[1]), ref) < TOL_IMAGE
+    assert p.status() == 0
+
+
 def test_checkpoint_interval_invariance(torch):
     """Results do not depend on the checkpoint interval K: recomputed
     wavefields equal the stored ones bit for bit.  Even K runs two time steps
