@@ -286,6 +286,34 @@ def psf_combs(g: PsfGrid) -> np.ndarray:
     return out
 
 
+@dataclass(frozen=True)
+class Prior:
+    """Matern prior precision R = (delta I - gamma Lap_h)^2 on an nz x nx
+    model grid of spacing h (Section 2; alpha = 2), Lap_h the 5-point
+    Laplacian with mirrored (zero-flux) edges."""
+
+    nz: int
+    nx: int
+    h: float
+    delta: float
+    gamma: float
+
+
+def matern_prior(nz, nx, h, corr_length, std) -> Prior:
+    """delta and gamma from a correlation length and a pointwise standard
+    deviation, by the continuous Matern relations for alpha = 2 in 2-D
+    (smoothness nu = 1): kappa = sqrt(8 nu) / rho, sigma^2 =
+    1 / (4 pi kappa^2 gamma^2), delta = kappa^2 gamma."""
+    kappa = math.sqrt(8.0) / corr_length
+    gamma = 1.0 / (std * kappa * math.sqrt(4.0 * math.pi))
+    return Prior(nz, nx, h, kappa * kappa * gamma, gamma)
+
+
+def gaussian_probes(nz, nx, count, seed) -> np.ndarray:
+    """count N(0, 1) fields: the random test matrix of a randomized method."""
+    return np.random.default_rng(seed).standard_normal((count, nz, nx))
+
+
 def rademacher_smoothed(nz, nx, seeds, sigma=5.0) -> np.ndarray:
     out = []
     for s in seeds:
