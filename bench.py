@@ -107,9 +107,18 @@ def cpu_baseline(g, m, v, threads, nt_sample):
     oracle.gn_hvp(gs, m, v, nthreads=threads)
     dt = time.perf_counter() - t0
     frac = (threads * (nt_sample - 1)) / (g.ns * (g.nt - 1))
+    # the same on one core (one shot, 60 % of the steps): the per-core rate
+    g1 = g.with_shots([0]).with_nt(max(2, int(0.6 * nt_sample)))
+    t1 = time.perf_counter()
+    oracle.gn_hvp(g1, m, v, nthreads=1)
+    dt1 = time.perf_counter() - t1
+    frac1 = (g1.nt - 1) / (g.ns * (g.nt - 1))
     return {"value": frac / dt, "unit": "Hv/s", "cores": threads, "kind": "oracle",
             "sample": f"one GN Hv on {threads} of {g.ns} shots, full 921x301 grid, "
-                      f"{nt_sample} of {g.nt} steps, {dt:.1f} s wall; scaled by shot-steps"}
+                      f"{nt_sample} of {g.nt} steps, {dt:.1f} s wall; scaled by shot-steps",
+            "per_core_value": frac1 / dt1,
+            "per_core_sample": f"one shot, {g1.nt} steps, 1 thread, {dt1:.1f} s wall; "
+                               f"scaled by shot-steps"}
 
 
 def calibrate_copy(nbytes=2 << 30, reps=5):
@@ -345,6 +354,85 @@ def psf_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def lowrank_bench(args):
+    """Low-rank row (Section 3.1) on the 921x301 / 64-shot / 4000-step
+    workload at the smoothed model: the r = 100 leading eigenpairs of
+    H_d v = lambda R v (Matern prior, correlation length 500 m, pointwise
+    standard deviation 200 m/s) from k = r + 10 Gaussian probes by the double
+    pass (2k Hessian products), then the approximations of Section 3.1
+    applied to batches of 16 vectors."""
+    import torch
+    from paper_2507_10804_amd import fwi, synth
+    from paper_2507_10804_amd import lowrank as glr
+
+    g, m_true, m_eval = synth.config_layered(nt=args.nt)
+    r = args.rank
+    k = r + 10
+    P = synth.matern_prior(g.nz, g.nx, g.dx, 500.0, 200.0)
+    dev = torch.device("cuda:0")
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    me = f32(m_eval)
+    omega = f32(synth.gaussian_probes(g.nz, g.nx, k, seed=300))
+    gp = glr.Prior(P, device=dev)
+    plan.profile(True)
+    plan.profile_reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lr = glr.LowRank(plan, me, gp, omega, r)
+    torch.cuda.synchronize()
+    t_build = time.perf_counter() - t0
+    nseg = (g.nt - 1 + plan.K - 1) // plan.K
+    kern = _kernel_table(plan, 1, None)
+    plan.profile(False)
+    plan.release_workspaces()
+    del omega
+    lam = lr.lam.cpu().numpy()
+    log(f"lowrank: kept {lr.kept} of {k}, build {t_build:.1f} s, {lr.timing_ms}")
+    V16 = f32(synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, 17)))
+    apply_ms = {}
+    for name, fn in (("hessian", lr.hessian), ("inverse", lr.inverse), ("sample", lr.sample)):
+        fn(V16)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(5):
+            fn(V16)
+        e1.record()
+        torch.cuda.synchronize()
+        apply_ms[name] = e0.elapsed_time(e1) / 5
+    n_hv = k + lr.kept
+    dom = max(kern, key=lambda n: kern[n]["total_ms_per_step"])
+    out = {"metric": "rank-100 low-rank approximation of H_d (generalized eigenpairs): build time",
+           "unit": "s", "value": t_build, "n_gpus": 1, "steps": 1, "warmup": 0,
+           "ms_per_step": t_build * 1e3, "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32 (FP64 algebra)", "data": "synthetic",
+           "config": {"workload": f"layered-faulted 921x301 at the smoothed model, {g.ns} shots, "
+                                  f"nt={g.nt}; Matern prior rho=500 m sigma=200 m/s; "
+                                  f"r={r}, k={k} Gaussian probes, double pass",
+                      "rank": r, "probes": k, "kept": lr.kept},
+           "hessian_products": n_hv, "hv_per_s_in_build": n_hv / t_build,
+           "phase_ms": lr.timing_ms,
+           "algebra_ms": lr.timing_ms["range"] + lr.timing_ms["project"],
+           "apply_ms_per_16_vectors": apply_ms,
+           "eigenvalues": {"first": float(lam[0]), "tenth": float(lam[9]),
+                           "last": float(lam[-1])},
+           "kernels": {n: {kk: vv for kk, vv in v.items()} for n, v in kern.items()},
+           "roofline": {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": None, "traffic": None,
+                        "avg_launch_us": kern[dom]["avg_us"],
+                        "note": "the Hessian products dominate; their kernels' roofline is the "
+                                "default mode's"}}
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(g, m_eval, synth.smooth_random((g.nz, g.nx), seed=1),
+                            min(16, len(os.sched_getaffinity(0))), args.cpu_nt)
+        out["cpu_baseline"] = {"value": n_hv / base["value"], "unit": "s", "cores": base["cores"],
+                               "kind": "oracle",
+                               "sample": base["sample"] + f"; build time = {n_hv} products at "
+                                                          "that rate (algebra not counted)"}
+    print(json.dumps(out), flush=True)
+
+
 def algorithmic_bytes_hvp(g, B, nseg):
     """Algorithmic bytes of one B-vector Hessian-vector call alone (forward
     + Born, recompute, adjoint), per kernel kind (see algorithmic_bytes)."""
@@ -422,13 +510,15 @@ def main():
     ap.add_argument("--shots", type=int, default=64)
     ap.add_argument("--nt", type=int, default=4000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-nt", type=int, default=300)
+    ap.add_argument("--cpu-nt", type=int, default=1000)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-launch HIP events (rocprofv3 runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
-    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd", "psf"], default="hvp")
+    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd", "psf", "lowrank"],
+                    default="hvp")
+    ap.add_argument("--rank", type=int, default=100)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -445,6 +535,8 @@ def main():
         return
     if args.mode == "psf":
         return psf_bench(args)
+    if args.mode == "lowrank":
+        return lowrank_bench(args)
     if args.mode == "autograd":
         autograd_bench(args)
         return
