@@ -1,5 +1,6 @@
-"""Thin ctypes binding of the C ABI in ``include/fwi.h`` (and the PSF entry
-points of ``include/fwi_psf.h``, wrapped in :mod:`.psf`).
+"""Thin ctypes binding of the C ABI in ``include/fwi.h`` (and of the PSF and
+low-rank entry points of ``include/fwi_psf.h`` and ``include/fwi_lowrank.h``,
+wrapped in :mod:`.psf` and :mod:`.lowrank`).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``libfwi_mi355x.so``.  PyTorch supplies device memory (plan block,
@@ -26,7 +27,10 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_adjoint", "fwi_misfit_grad", "fwi_gn_hvp", "fwi_status", "fwi_strerror",
            "fwi_last_error", "fwi_profile_enable", "fwi_profile_read", "fwi_profile_reset",
            "fwi_forward_keep", "fwi_adjoint_resume", "fwi_misfit", "fwi_kernel_steps",
-           "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply", "fwi_misfit_grad_hvp"]
+           "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply", "fwi_misfit_grad_hvp",
+           "fwi_prior_create", "fwi_prior_destroy", "fwi_prior_device_bytes", "fwi_prior_bind",
+           "fwi_prior_workspace_size", "fwi_prior_apply", "fwi_lowrank_workspace_size",
+           "fwi_lowrank_range", "fwi_lowrank_project", "fwi_lowrank_apply"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -58,7 +62,7 @@ def load_library(path: str = LIB_PATH):
         if not os.path.exists(path):
             raise FwiError(-4, f"{path} not built: run __graft_entry__.build()")
         lib = ctypes.CDLL(path)
-        P, I, Z = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        P, I, Z, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
         sig = {
             "fwi_abi_version": ([], I),
             "fwi_plan_create": ([P, P], I),
@@ -84,6 +88,16 @@ def load_library(path: str = LIB_PATH):
             "fwi_kernel_steps": ([P, I, P], I),
             "fwi_misfit_grad_hvp": ([P, P, P, P, I, P, P, P, P, Z, P], I),
             "fwi_psf_check": ([P], I),
+            "fwi_prior_create": ([ctypes.c_int32, ctypes.c_int32, D, D, D, P], I),
+            "fwi_prior_destroy": ([P], None),
+            "fwi_prior_device_bytes": ([P, P], I),
+            "fwi_prior_bind": ([P, P, Z, P], I),
+            "fwi_prior_workspace_size": ([P, I, P], I),
+            "fwi_prior_apply": ([P, I, P, I, P, P, Z, P], I),
+            "fwi_lowrank_workspace_size": ([P, I, I, I, P], I),
+            "fwi_lowrank_range": ([P, I, P, D, P, P, P, P, Z, P], I),
+            "fwi_lowrank_project": ([P, I, P, P, I, P, P, P, Z, P], I),
+            "fwi_lowrank_apply": ([P, I, P, P, I, P, I, P, P, Z, P], I),
             "fwi_psf_extract": ([P, P, P, P], I),
             "fwi_psf_apply": ([P, P, P, I, P, P], I),
         }

@@ -1,0 +1,187 @@
+"""Matern prior and low-rank approximation on the GPU against the FP64 oracle
+(oracle/lowrank.py).
+
+* prior operators R, R^-1, A^-1 on seeded white fields, small and full-size
+  grids: rel-L2 < 1e-5 (FP64 accumulation of FP32 data; R^-1 of white noise
+  is dominated by well-resolved low frequencies);
+* the algebra of the double pass fed with the same Hessian images on both
+  sides (a dense SPD operator with a controlled spectrum on a small grid;
+  the GPU's Q goes through the same operator on the host): leading
+  eigenvalues to 1e-5 and the approximations to 1e-4;
+* the three approximations of Section 3.1 from given eigenpairs: 1e-5;
+* end to end on the 128 x 128 / 4-shot wave problem, GPU Hessian products
+  against oracle ones: leading eigenvalues to 1e-3 (FP32 wave solves carry
+  ~1e-5 relative error, which R^-1 amplifies in the low frequencies).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lowrank as LR
+from paper_2507_10804_amd import synth
+from tests._cases import rel
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def dev(torch, a):
+    # C-contiguous: some arrays here are transposed views, and the raw
+    # ABI calls below read device memory in row-major order
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def host(x):
+    return x.detach().double().cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(37, 45, 10.0, 80.0, 5.0), (301, 921, 10.0, 500.0, 200.0),
+                                   (1, 7, 3.0, 10.0, 1.0)])
+def test_prior_operators(shape):
+    import torch
+    from paper_2507_10804_amd import lowrank as glr
+
+    nz, nx, h, rho, sd = shape
+    P = synth.matern_prior(nz, nx, h, rho, sd)
+    say(f"case: fwi_prior_apply {nz}x{nx}")
+    gp = glr.Prior(P)
+    op = LR.Prior(P)
+    w = synth.gaussian_probes(nz, nx, 3, seed=nz + nx)
+    wd = dev(torch, w)
+    w32 = np.float32(w).astype(np.float64)
+    for kind, ref in ((glr.PRIOR_R, op.apply(w32)), (glr.PRIOR_RINV, op.solve(w32)),
+                      (glr.PRIOR_AINV, op.sqrt_inv(w32))):
+        got = host(gp.apply(kind, wd))
+        e = rel(got, ref)
+        say(f"  op {kind}: rel-L2 {e:.2e}")
+        assert e < 1e-5
+
+
+def _dense_case(nz=12, nx=14, rank=None, seed=3):
+    P = synth.matern_prior(nz, nx, 10.0, 60.0, 4.0)
+    n = nz * nx
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    d = 1e-2 * np.geomspace(1.0, 1e-2, n)
+    H = (U * d) @ U.T
+    return P, 0.5 * (H + H.T)
+
+
+def test_double_pass_algebra_matches_oracle():
+    """Same operator on both sides: the GPU range, eigenproblem and products
+    against the oracle's double pass on the same probes."""
+    import torch
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import lowrank as glr
+
+    P, H = _dense_case()
+    nz, nx = P.nz, P.nx
+    k, r = 24, 10
+    say(f"case: fwi_lowrank_range/project on a dense pencil, {nz}x{nx}, k={k}, r={r}")
+    omega = synth.gaussian_probes(nz, nx, k, seed=5)
+    Hop = lambda X: (H @ np.asarray(X, np.float64).reshape(X.shape[0], -1).T).T.reshape(X.shape)
+    op = LR.Prior(P)
+    lam_o, V_o = LR.double_pass(Hop, op, np.float32(omega).astype(np.float64), r, tol=1e-7)
+
+    gp = glr.Prior(P)
+    lib = gp.lib
+    import ctypes
+    n = ctypes.c_size_t()
+    fwi._check(lib.fwi_lowrank_workspace_size(gp._h, k, 1, r, ctypes.byref(n)))
+    ws = torch.empty(n.value, dtype=torch.uint8, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    p = lambda x: ctypes.c_void_p(x.data_ptr())
+    ybar = dev(torch, Hop(np.float32(omega).astype(np.float64)))
+    Q = torch.empty((k, nz, nx), dtype=torch.float32, device="cuda")
+    RQ = torch.empty_like(Q)
+    kept = torch.zeros((), dtype=torch.int32, device="cuda")
+    fwi._check(lib.fwi_lowrank_range(gp._h, k, p(ybar), 1e-7, p(Q), p(RQ), p(kept), p(ws),
+                                     n.value, st))
+    kq = int(kept.item())
+    Qh = host(Q[:kq])
+    R = op.apply(Qh)
+    G = Qh.reshape(kq, -1) @ R.reshape(kq, -1).T
+    say(f"  kept {kq} of {k}; |Q R Q^T - I|_max = {np.abs(G - np.eye(kq)).max():.2e}")
+    assert kq >= r and np.abs(G - np.eye(kq)).max() < 1e-4
+    hq = dev(torch, Hop(Qh))
+    lam = torch.empty(r, dtype=torch.float64, device="cuda")
+    V = torch.empty((r, nz, nx), dtype=torch.float32, device="cuda")
+    Qk = Q[:kq].contiguous()
+    fwi._check(lib.fwi_lowrank_project(gp._h, kq, p(Qk), p(hq), r, p(lam), p(V), p(ws), n.value,
+                                       st))
+    lam_g = host(lam)
+    e_lam = np.abs(lam_g - lam_o) / lam_o
+    say(f"  leading eigenvalues: max rel {e_lam.max():.2e}")
+    assert e_lam.max() < 1e-5
+    # eigenvectors up to sign through the operator they define
+    v = synth.smooth_random((nz, nx), seed=9, sigma=2.0)
+    lr = glr.LowRank.from_pairs(gp, lam, V)
+    for name, fn_g, fn_o in (("hessian", lr.hessian, LR.hessian_apply),
+                             ("inverse", lr.inverse, LR.inverse_apply),
+                             ("sample", lr.sample, LR.sample)):
+        got = host(fn_g(dev(torch, v)))
+        ref = fn_o(op, lam_o, V_o, np.float32(v).astype(np.float64))
+        e = rel(got, ref)
+        say(f"  {name}: rel-L2 {e:.2e}")
+        assert e < 1e-4
+
+
+def test_approximations_from_given_pairs():
+    import torch
+    from paper_2507_10804_amd import lowrank as glr
+
+    P = synth.matern_prior(40, 52, 10.0, 100.0, 10.0)
+    op = LR.Prior(P)
+    r = 7
+    rng = np.random.default_rng(2)
+    V = op.sqrt_inv(rng.standard_normal((r, P.nz, P.nx)))  # R-scaled basis (not orthonormal:
+    lam = np.geomspace(50.0, 0.5, r)                         # the formulas are linear in V)
+    V32 = np.float32(V).astype(np.float64)
+    gp = glr.Prior(P)
+    lr = glr.LowRank.from_pairs(gp, torch.as_tensor(lam, device="cuda"), dev(torch, V))
+    w = synth.gaussian_probes(P.nz, P.nx, 4, seed=8)
+    w32 = np.float32(w).astype(np.float64)
+    say("case: fwi_lowrank_apply from given pairs, 40x52, r=7, B=4")
+    for name, fn_g, fn_o in (("hessian", lr.hessian, LR.hessian_apply),
+                             ("inverse", lr.inverse, LR.inverse_apply),
+                             ("sample", lr.sample, LR.sample)):
+        got = host(fn_g(dev(torch, w)))
+        for b in range(4):
+            e = rel(got[b], fn_o(op, lam, V32, w32[b]))
+            assert e < 1e-5, f"{name} vector {b}: {e:.2e}"
+        say(f"  {name}: ok")
+
+
+def test_end_to_end_wave_hessian():
+    import torch
+    import oracle
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import lowrank as glr
+
+    g, m_true, m_eval = synth.config_small()
+    P = synth.matern_prior(g.nz, g.nx, g.dx, 300.0, 100.0)
+    k, r = 20, 8
+    say(f"case: LowRank 128x128, 4 shots, nt={g.nt}, k={k}, r={r} vs the oracle's double pass")
+    omega = synth.gaussian_probes(g.nz, g.nx, k, seed=11)
+    plan = fwi.Plan(g)
+    gp = glr.Prior(P)
+    lr = glr.LowRank(plan, dev(torch, m_eval), gp, dev(torch, omega), r, tol=1e-7)
+    m32 = np.float32(m_eval).astype(np.float64)
+    hv = lambda X: np.stack([oracle.gn_hvp(g, m32, x) for x in np.asarray(X)])
+    lam_o, V_o = LR.double_pass(hv, LR.Prior(P), np.float32(omega).astype(np.float64), r,
+                                tol=1e-7)
+    lam_g = host(lr.lam)
+    e = np.abs(lam_g - lam_o) / lam_o
+    say(f"  kept {lr.kept}; eigenvalues {lam_o[0]:.3e}..{lam_o[-1]:.3e}; max rel {e.max():.2e}")
+    assert e.max() < 1e-3
+    v = synth.smooth_random((g.nz, g.nx), seed=4, sigma=5.0)
+    got = host(lr.inverse(dev(torch, v)))
+    ref = LR.inverse_apply(LR.Prior(P), lam_o, V_o, np.float32(v).astype(np.float64))
+    ei = rel(got, ref)
+    say(f"  inverse apply rel-L2 {ei:.2e}")
+    assert ei < 1e-3
