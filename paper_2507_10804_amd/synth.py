@@ -309,6 +309,49 @@ def matern_prior(nz, nx, h, corr_length, std) -> Prior:
     return Prior(nz, nx, h, kappa * kappa * gamma, gamma)
 
 
+@dataclass(frozen=True)
+class SymbolGrid:
+    """Periodic FFT grid of mz x mx cells of spacing h whose first nz rows and
+    nx columns hold the model grid (the rest is zero padding), and the
+    sampling of the symbol columns: r equally spaced directions on the circle
+    of radius rho0 (angular wavenumber, rad per unit length)."""
+
+    nz: int
+    nx: int
+    mz: int
+    mx: int
+    h: float
+    r: int = 8
+    rho0: float = 0.0
+
+
+def fft_size(n: int) -> int:
+    """Smallest m >= n whose prime factors are 2, 3 and 5."""
+    m = max(int(n), 1)
+    while True:
+        k = m
+        for p in (2, 3, 5):
+            while k % p == 0:
+                k //= p
+        if k == 1:
+            return m
+        m += 1
+
+
+def symbol_grid(nz, nx, h, pad, r=8, rho0=0.0) -> SymbolGrid:
+    """FFT grid with at least `pad` cells of zero padding after the model in
+    each direction (pad >= the half width of a PSF window keeps circular
+    correlations with such windows free of wrap-around)."""
+    return SymbolGrid(nz, nx, fft_size(nz + pad), fft_size(nx + pad), float(h), int(r),
+                      float(rho0))
+
+
+def probe_radius(f_max: float, c_max: float) -> float:
+    """Angular wavenumber 2 pi f_max / c_max of the shortest wavelength the
+    band reaches at the highest velocity."""
+    return 2.0 * math.pi * f_max / c_max
+
+
 def gaussian_probes(nz, nx, count, seed) -> np.ndarray:
     """count N(0, 1) fields: the random test matrix of a randomized method."""
     return np.random.default_rng(seed).standard_normal((count, nz, nx))
