@@ -433,6 +433,124 @@ def lowrank_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def symbol_apply_bytes(G, B, T):
+    """Algorithmic HBM bytes of one low-rank symbol apply of B vectors with T
+    terms: every pass reads its inputs and writes its outputs once (forward
+    rows: v -> row spectra of the nz data rows; forward columns: -> the
+    mz x mx spectrum; inverse columns: spectrum and T tables -> T partial
+    transforms of the nz model rows; inverse rows: those and the T
+    coefficient fields -> out).  complex64 = 8 bytes, float32 = 4."""
+    nz, nx, mz, mx = G.nz, G.nx, G.mz, G.mx
+    return (4 * B * nz * nx + 8 * B * nz * mx            # rows forward
+            + 8 * B * nz * mx + 8 * B * mz * mx          # columns forward
+            + 8 * B * mz * mx + 8 * T * mz * mx + 8 * B * T * nz * mx   # columns inverse
+            + 8 * B * T * nz * mx + 8 * T * nz * nx + 4 * B * nz * nx)  # rows inverse
+
+
+def symbol_bench(args):
+    """PDO and PSF+ rows (Sections 3.4, 3.6, Appendix A) on the 921x301 /
+    64-shot / 4000-step workload at the smoothed model: one batched Hessian
+    product of the sinusoid probe (r = 8 directions at rho0 = 2 pi f_max /
+    c_max, f_max = 2.5 f0) and the 4 PSF combs; symbol columns, PSF
+    extraction (9 x 29 lattice, 63 x 63 windows) and the PSF+ tables of rank
+    `--symbol-rank` on the device; then both approximations applied to
+    batches of smooth vectors through the FFT chain (360 x 960 FFT grid)."""
+    import torch
+    from oracle import pdo as D
+    from paper_2507_10804_amd import fwi, synth
+    from paper_2507_10804_amd import psf as gpsf
+    from paper_2507_10804_amd import symbol as S
+
+    g, m_true, m_eval = synth.config_layered(nt=args.nt)
+    pg = synth.psf_grid(g.nz, g.nx)
+    G = synth.symbol_grid(g.nz, g.nx, g.dx, pg.half, r=8,
+                          rho0=synth.probe_radius(2.5 * g.f0, float(m_eval.max())))
+    rank = args.symbol_rank
+    dev = torch.device("cuda:0")
+    plan = fwi.Plan(g, device=dev)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    me = f32(m_eval)
+    sym = S.Symbol(G, device=dev)
+    probes = torch.cat([sym.pdo_probe()[None], f32(synth.psf_combs(pg))])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hv = plan.gn_hvp(me, probes)
+    torch.cuda.synchronize()
+    t_hv = time.perf_counter() - t0
+    plan.release_workspaces()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    ev[0].record()
+    pdo_op, cols = S.pdo(sym, hv[0])
+    ev[1].record()
+    psf = gpsf.extract(pg, hv[1:].contiguous())
+    ev[2].record()
+    pp_op, info = S.psf_plus(sym, pg, psf, cols, rank)
+    ev[3].record()
+    torch.cuda.synchronize()
+    build_ms = {"pdo_columns": ev[0].elapsed_time(ev[1]), "psf_extract": ev[1].elapsed_time(ev[2]),
+                "psf_plus_tables": ev[2].elapsed_time(ev[3])}
+    info_h = info.cpu().numpy()
+    log(f"symbol: 5 Hessian products {t_hv:.1f} s; build {build_ms}; alpha {info_h[0]:.3e}")
+    B = args.batch
+    V = f32(synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, B + 1)))
+    out_buf = torch.empty_like(V)
+    res = {}
+    reps = max(10, args.steps)
+    for name, op in (("pdo", pdo_op), ("psf_plus", pp_op)):
+        for bb in (1, B):
+            for _ in range(args.warmup + 1):
+                op(V[:bb], out=out_buf[:bb])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                op(V[:bb], out=out_buf[:bb])
+            e1.record()
+            torch.cuda.synchronize()
+            res[(name, bb)] = e0.elapsed_time(e1) / reps
+            log(f"symbol: {name} apply, {bb} vectors: {res[(name, bb)]:.3f} ms")
+    # quality against true products (information, not parity)
+    hv4 = plan.gn_hvp(me, V[:4])
+    plan.release_workspaces()
+    psf_approx = gpsf.apply(pg, psf, V[:4])
+    q = {}
+    for name, a in (("psf", psf_approx), ("pdo", pdo_op(V[:4])), ("psf_plus", pp_op(V[:4]))):
+        q[name] = [float((a[i] - hv4[i]).norm() / hv4[i].norm()) for i in range(4)]
+    T = pp_op.terms
+    ms = res[("psf_plus", B)]
+    nbytes = symbol_apply_bytes(G, B, T)
+    achieved = nbytes / (ms * 1e-3) / 1e9
+    out = {"metric": "PSF+-approximate H_d v applies/s", "unit": "applies/s",
+           "value": B / (ms * 1e-3), "n_gpus": 1, "steps": reps, "warmup": args.warmup,
+           "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32 (FP64 algebra)", "data": "synthetic",
+           "config": {"workload": f"layered-faulted 921x301 at the smoothed model, {g.ns} shots, "
+                                  f"nt={g.nt}; PDO r=8 at rho0={G.rho0:.4g} rad/m; PSF lattice "
+                                  f"{pg.nzc}x{pg.nxc} window {pg.width}; PSF+ rank {rank}; FFT "
+                                  f"grid {G.mz}x{G.mx}; apply to {B} smooth vectors per call",
+                      "batch": B, "rank": rank, "terms": T, "fft_grid": [G.mz, G.mx]},
+           "hessian_products_s": t_hv, "build_ms": build_ms,
+           "alpha": float(info_h[0]), "kept": int(info_h[1]),
+           "apply_ms": {f"{n}_B{b}": v for (n, b), v in res.items()},
+           "rel_error_vs_true_hv": q,
+           "roofline": {"bound": "hbm", "kernel": "fwi_symbol_apply (4 launches)",
+                        "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                        "alg_bytes_per_call": nbytes, "avg_call_us": ms * 1e3}}
+    if not args.no_cpu_baseline:
+        A_h = pp_op.A.cpu().numpy().astype(np.complex128)
+        M_h = pp_op.M.cpu().numpy().astype(np.complex128)
+        v_h = V[0].double().cpu().numpy()
+        t1 = time.perf_counter()
+        D.symbol_apply(G, A_h, M_h, v_h)
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": 1.0 / dt, "unit": "applies/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"one vector through the FP64 oracle's low-rank symbol "
+                                         f"apply with the same {T} tables, {dt:.2f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def algorithmic_bytes_hvp(g, B, nseg):
     """Algorithmic bytes of one B-vector Hessian-vector call alone (forward
     + Born, recompute, adjoint), per kernel kind (see algorithmic_bytes)."""
@@ -516,9 +634,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
-    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd", "psf", "lowrank"],
-                    default="hvp")
+    ap.add_argument("--mode", choices=["hvp", "serve", "probing", "autograd", "psf", "lowrank",
+                                       "symbol"], default="hvp")
     ap.add_argument("--rank", type=int, default=100)
+    ap.add_argument("--symbol-rank", type=int, default=16)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
@@ -537,6 +656,8 @@ def main():
         return psf_bench(args)
     if args.mode == "lowrank":
         return lowrank_bench(args)
+    if args.mode == "symbol":
+        return symbol_bench(args)
     if args.mode == "autograd":
         autograd_bench(args)
         return

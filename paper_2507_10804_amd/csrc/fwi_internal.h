@@ -149,4 +149,35 @@ struct AdjArgs {
   int order;          // workgroup order: 0 vector-major, 1 tile-major, 2 blocked
 };
 
+// Dense products for the approximation layers (defined with the low-rank
+// code): C(i, j) = alpha sum_p A(i, p) B(p, j) + beta C(i, j) over a batch,
+// X(i, j) = X[b * xb + i * x1 + j * x2], FP32 operands read through LDS
+// tiles, FP64 accumulation.  In split mode (part != null) the batch index
+// runs over chunks of the inner dimension instead and each chunk writes its
+// FP64 partial sum to part[chunk][M][N].
+struct Gemm {
+  int M, N, K;
+  const float *A;
+  long long ab, am, ak;
+  const float *B;
+  long long bb, bk, bn;
+  float *C;
+  long long cb, cm, cn;
+  float alpha, beta;
+  double *part;  // split mode: [nchunk][M][N]
+  int kchunk;    // inner-dimension length per chunk (split mode)
+};
+constexpr int KCHUNK = 4096;  // inner-dimension chunk of the long products
+Gemm plain(int M, int N, int K);  // alpha 1, beta 0, zero strides
+hipError_t gemm(const Gemm &g, int batch, hipStream_t st);
+int nchunks(long long K);
+// out[M][N] (FP64) = A B over a long inner dimension, via FP64 partials.
+hipError_t gemm_long(Gemm g, double *part, double *out, hipStream_t st);
+
+// Eigenpairs of the symmetric k x k FP64 matrix A (overwritten; k <=
+// EIG_KMAX) by parallel cyclic Jacobi: eigenvalues descending in w[k], the
+// matching eigenvectors as the columns of Zs[k][k]; Z[k][k] is scratch.
+constexpr int EIG_KMAX = 512;
+hipError_t sym_eig(int k, double *A, double *Z, double *w, double *Zs, hipStream_t st);
+
 }  // namespace fwi

@@ -30,23 +30,6 @@ constexpr size_t LR_ALIGN = 256;
 size_t lr_align(size_t v) { return (v + LR_ALIGN - 1) / LR_ALIGN * LR_ALIGN; }
 
 // --------------------------------------------------------------------- GEMM
-// C(i, j) = alpha sum_p A(i, p) B(p, j) + beta C(i, j) over a batch, with
-// X(i, j) = X[b * sb + i * s1 + j * s2].  In split mode (part != null) the
-// third grid dimension indexes chunks of the inner dimension and each chunk
-// writes its FP64 partial sum to part[chunk][M][N] instead.
-struct Gemm {
-  int M, N, K;
-  const float *A;
-  long long ab, am, ak;
-  const float *B;
-  long long bb, bk, bn;
-  float *C;
-  long long cb, cm, cn;
-  float alpha, beta;
-  double *part;  // split mode: [nchunk][M][N]
-  int kchunk;    // inner-dimension length per chunk (split mode)
-};
-
 constexpr int GT = 64;   // output tile edge
 constexpr int GK = 16;   // inner-dimension slice staged per step
 
@@ -122,14 +105,14 @@ __global__ void k_sum_parts(const double *__restrict__ part, int nchunk, long lo
   }
 }
 
+}  // namespace
+
 hipError_t gemm(const Gemm &g, int batch, hipStream_t st) {
   const dim3 grid((unsigned)((g.N + GT - 1) / GT), (unsigned)((g.M + GT - 1) / GT),
                   (unsigned)batch);
   hipLaunchKernelGGL(k_gemm, grid, dim3(256), 0, st, g);
   return hipGetLastError();
 }
-
-constexpr int KCHUNK = 4096;
 
 int nchunks(long long K) { return (int)((K + KCHUNK - 1) / KCHUNK); }
 
@@ -145,6 +128,18 @@ hipError_t gemm_long(Gemm g, double *part, double *out, hipStream_t st) {
                      dim3(256), 0, st, part, nc, n, out);
   return hipGetLastError();
 }
+
+Gemm plain(int M, int N, int K) {
+  Gemm g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.alpha = 1.0f;
+  g.beta = 0.0f;
+  return g;
+}
+
+namespace {
 
 // ------------------------------------------------------------------- prior
 struct PriorGeo {
@@ -188,7 +183,6 @@ __global__ void k_prior_scale(const float *__restrict__ spec, long long plane, i
 // in descending order in w[k] and the matching eigenvectors as the columns
 // of Zs (k x k); Z is scratch.  At most max_sweeps sweeps.
 constexpr int EIG_T = 1024;
-constexpr int EIG_KMAX = 512;
 
 __global__ __launch_bounds__(EIG_T) void k_symeig(int k, double *__restrict__ A,
                                                   double *__restrict__ Z, double *__restrict__ w,
@@ -358,6 +352,12 @@ __global__ void k_copy_f(float *__restrict__ dst, const float *__restrict__ src,
 unsigned blocks(long long n) { return (unsigned)std::min<long long>((n + 255) / 256, 16384); }
 
 }  // namespace
+
+hipError_t sym_eig(int k, double *A, double *Z, double *w, double *Zs, hipStream_t st) {
+  hipLaunchKernelGGL(k_symeig, dim3(1), dim3(EIG_T), 0, st, k, A, Z, w, Zs, 60, 1e-14);
+  return hipGetLastError();
+}
+
 }  // namespace fwi
 
 using namespace fwi;
@@ -390,16 +390,6 @@ void dct_matrix(int n, float *C) {
     const double cp = (p == 0 ? std::sqrt(1.0 / n) : std::sqrt(2.0 / n));
     for (int i = 0; i < n; ++i) C[(size_t)p * n + i] = (float)(cp * std::cos(M_PI * p * (i + 0.5) / n));
   }
-}
-
-Gemm plain(int M, int N, int K) {
-  Gemm g{};
-  g.M = M;
-  g.N = N;
-  g.K = K;
-  g.alpha = 1.0f;
-  g.beta = 0.0f;
-  return g;
 }
 
 // R^-1 (power 2) or A^-1 (power 1) of B planes: DCT along x and z as GEMMs,
@@ -601,10 +591,8 @@ static int gram(int k, long long n, const float *X, const float *Y, void *ws, co
 }
 
 static int symeig(int k, void *ws, const LrLayout &L, hipStream_t st) {
-  hipLaunchKernelGGL(k_symeig, dim3(1), dim3(EIG_T), 0, st, k, at_<double>(ws, L.G),
-                     at_<double>(ws, L.Z), at_<double>(ws, L.w), at_<double>(ws, L.Zs), 60,
-                     1e-14);
-  LR_TRY(hipGetLastError());
+  LR_TRY(sym_eig(k, at_<double>(ws, L.G), at_<double>(ws, L.Z), at_<double>(ws, L.w),
+                 at_<double>(ws, L.Zs), st));
   return FWI_OK;
 }
 

@@ -1,0 +1,1001 @@
+// Low-rank symbol approximations of the misfit Hessian on gfx950: the FFT
+// apply of Section 3.3 (eq. "lr-psido"), PDO probing (Section 3.4, Appendix
+// A) and the PSF+ least squares (Section 3.6).  The ABI and the exact
+// definitions are in fwi_symbol.h.
+//
+// FFT engine.  Complex FP32 transforms of lengths up to 2048 with factors 2,
+// 3 and 5, done in LDS: a workgroup stages whole lines -- one row, or a band
+// of adjacent columns read row by row so that global reads stay contiguous --
+// and runs self-sorting Stockham stages (radix 4, 2, 3, 5) between two LDS
+// buffers.  A 2-D transform is a row pass and a column pass.  The zero
+// padding of the FFT grid is never read (rows beyond the data are filled in
+// LDS) and the inverse passes store only model-grid rows and columns.  The
+// pointwise products with the symbol tables happen on the loads of the
+// inverse column pass, and the blend sum_t Re(A_t z_t) on the stores of the
+// inverse row pass, so an apply is four launches.  These are HBM/L2-bound
+// data movements with O(log n) flops per element: no dense contraction, no
+// MFMA.
+#include "fwi.h"
+#include "fwi_internal.h"
+#include "fwi_psf.h"
+#include "fwi_symbol.h"
+
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+namespace fwi {
+namespace {
+
+constexpr int FFT_MAXN = 2048;
+constexpr int FFT_MAXST = 12;
+constexpr int SYM_RMAX = 16;   // PDO directions
+constexpr int PP_RANK = 32;    // PSF+ rank
+constexpr int NTH = 256;
+constexpr int LDS_BUDGET = 65536;
+constexpr double TIE = 1e-9;   // relative distance tolerance of the separation
+
+struct Fft1 {
+  int n, ns;
+  int radix[FFT_MAXST];
+  const float2 *tw;  // e^{-2 pi i m / n}, m < n
+};
+
+struct SymGeo {
+  int nz, nx, mz, mx, r;
+  double h, rho0;
+  Fft1 fz, fx;
+  double sx[SYM_RMAX / 2], sz[SYM_RMAX / 2];  // xi_k for k = 1..r/2
+};
+
+__device__ inline float2 cmul(float2 a, float2 b) {
+  return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
+}
+__device__ inline float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ inline float2 csub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+// i z (forward sign folded by the caller)
+__device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }
+
+// R-point DFT in place, sign - (forward) or + (inverse).
+template <int R, bool INV>
+__device__ inline void dft(float2 *v) {
+  if constexpr (R == 2) {
+    const float2 a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+  } else if constexpr (R == 4) {
+    const float2 t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    const float2 t2 = cadd(v[1], v[3]), t3 = csub(v[1], v[3]);
+    const float2 it3 = INV ? cmuli(t3) : cmuli(make_float2(-t3.x, -t3.y));  // +-i t3
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, it3);
+    v[3] = csub(t1, it3);
+  } else if constexpr (R == 3) {
+    const float c = -0.5f;
+    const float s = INV ? 0.86602540378443865f : -0.86602540378443865f;
+    const float2 a = cadd(v[1], v[2]), b = csub(v[1], v[2]);
+    const float2 m = make_float2(fmaf(c, a.x, v[0].x), fmaf(c, a.y, v[0].y));
+    const float2 ib = cscale(cmuli(b), s);
+    v[0] = cadd(v[0], a);
+    v[1] = cadd(m, ib);
+    v[2] = csub(m, ib);
+  } else {  // R == 5
+    const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
+    const float s1 = INV ? 0.95105651629515357f : -0.95105651629515357f;
+    const float s2 = INV ? 0.58778525229247313f : -0.58778525229247313f;
+    const float2 a1 = cadd(v[1], v[4]), b1 = csub(v[1], v[4]);
+    const float2 a2 = cadd(v[2], v[3]), b2 = csub(v[2], v[3]);
+    const float2 m1 = make_float2(v[0].x + fmaf(c1, a1.x, c2 * a2.x), v[0].y + fmaf(c1, a1.y, c2 * a2.y));
+    const float2 m2 = make_float2(v[0].x + fmaf(c2, a1.x, c1 * a2.x), v[0].y + fmaf(c2, a1.y, c1 * a2.y));
+    const float2 n1 = cmuli(make_float2(fmaf(s1, b1.x, s2 * b2.x), fmaf(s1, b1.y, s2 * b2.y)));
+    const float2 n2 = cmuli(make_float2(fmaf(s2, b1.x, -s1 * b2.x), fmaf(s2, b1.y, -s1 * b2.y)));
+    v[0] = make_float2(v[0].x + a1.x + a2.x, v[0].y + a1.y + a2.y);
+    v[1] = cadd(m1, n1);
+    v[4] = csub(m1, n1);
+    v[2] = cadd(m2, n2);
+    v[3] = csub(m2, n2);
+  }
+}
+
+// One Stockham stage of radix R over `nlines` lines of length n (pitch
+// apart): sub-transforms of length Ns become length Ns*R, output in natural
+// order after the last stage.
+template <int R, bool INV>
+__device__ inline void stage(const float2 *src, float2 *dst, int pitch, int nlines, int n, int Ns,
+                             const float2 *tw) {
+  const int nR = n / R;
+  const int tstep = n / (Ns * R);
+  for (int e = threadIdx.x; e < nlines * nR; e += blockDim.x) {
+    const int line = e / nR;
+    const int j = e - line * nR;
+    const float2 *x = src + line * pitch;
+    float2 *y = dst + line * pitch;
+    const int k = j % Ns;
+    float2 v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = x[j + t * nR];
+    if (Ns > 1) {
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        float2 w = tw[k * t * tstep];
+        if (INV) w.y = -w.y;
+        v[t] = cmul(v[t], w);
+      }
+    }
+    dft<R, INV>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) y[base + t * Ns] = v[t];
+  }
+}
+
+// All stages; returns the buffer that holds the result.  Every thread of the
+// workgroup must call it (it synchronises after each stage).
+template <bool INV>
+__device__ float2 *fft_lines(float2 *a, float2 *b, int pitch, int nlines, const Fft1 &f,
+                             const float2 *tw) {
+  int Ns = 1;
+  for (int s = 0; s < f.ns; ++s) {
+    const int R = f.radix[s];
+    if (R == 4) stage<4, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else if (R == 2) stage<2, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else if (R == 3) stage<3, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else stage<5, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    __syncthreads();
+    float2 *t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
+__device__ inline void load_tw(float2 *dst, const Fft1 &f) {
+  for (int i = threadIdx.x; i < f.n; i += blockDim.x) dst[i] = f.tw[i];
+}
+
+// ------------------------------------------------------------- 2-D passes
+
+// Forward row transforms of B real planes in[b][rows][cols] (cols <= mx, zero
+// beyond): out[b][rows][mx].  One row per workgroup.
+__global__ __launch_bounds__(NTH) void k_rows_fwd(SymGeo g, const float *__restrict__ in, int rows,
+                                                  int cols, float2 *__restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int n = g.mx;
+  float2 *tw = sm, *a = sm + n, *b = a + n;
+  load_tw(tw, g.fx);
+  const long long row = (long long)blockIdx.y * rows + blockIdx.x;
+  const float *src = in + row * cols;
+  for (int i = threadIdx.x; i < n; i += NTH) a[i] = make_float2(i < cols ? src[i] : 0.0f, 0.0f);
+  __syncthreads();
+  const float2 *res = fft_lines<false>(a, b, n, 1, g.fx, tw);
+  float2 *dst = out + row * n;
+  for (int i = threadIdx.x; i < n; i += NTH) dst[i] = res[i];
+}
+
+// Forward column transforms: in[b][rows_in][mx] (rows beyond rows_in are
+// zero) to out[b][mz][mx].  A band of C adjacent columns per workgroup.
+__global__ __launch_bounds__(NTH) void k_cols_fwd(SymGeo g, const float2 *__restrict__ in,
+                                                  int rows_in, int C, float2 *__restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int n = g.mz, pitch = n + 1, mx = g.mx;
+  float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
+  load_tw(tw, g.fz);
+  const int col0 = blockIdx.x * C;
+  const long long bz = blockIdx.y;
+  for (int e = threadIdx.x; e < n * C; e += NTH) {
+    const int i = e / C, c = e - i * C;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (i < rows_in && col0 + c < mx) v = in[(bz * rows_in + i) * mx + col0 + c];
+    a[c * pitch + i] = v;
+  }
+  __syncthreads();
+  const float2 *res = fft_lines<false>(a, b, pitch, C, g.fz, tw);
+  for (int e = threadIdx.x; e < n * C; e += NTH) {
+    const int i = e / C, c = e - i * C;
+    if (col0 + c < mx) out[(bz * n + i) * mx + col0 + c] = res[c * pitch + i];
+  }
+}
+
+// Inverse column transforms of Mt[t] . spec[b], model rows stored:
+// z[b][t][nz][mx].  Grid (column bands, T, B).
+__global__ __launch_bounds__(NTH) void k_cols_inv(SymGeo g, const float2 *__restrict__ spec,
+                                                  const float2 *__restrict__ Mt, int T, int C,
+                                                  float2 *__restrict__ z) {
+  extern __shared__ float2 sm[];
+  const int n = g.mz, pitch = n + 1, mx = g.mx;
+  float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
+  load_tw(tw, g.fz);
+  const int col0 = blockIdx.x * C;
+  const long long t = blockIdx.y, bv = blockIdx.z;
+  const float2 *S = spec + bv * n * mx;
+  const float2 *W = Mt + t * n * mx;
+  for (int e = threadIdx.x; e < n * C; e += NTH) {
+    const int i = e / C, c = e - i * C;
+    float2 v = make_float2(0.0f, 0.0f);
+    if (col0 + c < mx) {
+      const long long o = (long long)i * mx + col0 + c;
+      v = cmul(S[o], W[o]);
+    }
+    a[c * pitch + i] = v;
+  }
+  __syncthreads();
+  const float2 *res = fft_lines<true>(a, b, pitch, C, g.fz, tw);
+  float2 *Z = z + (bv * T + t) * (long long)g.nz * mx;
+  for (int e = threadIdx.x; e < g.nz * C; e += NTH) {
+    const int i = e / C, c = e - i * C;
+    if (col0 + c < mx) Z[(long long)i * mx + col0 + c] = res[c * pitch + i];
+  }
+}
+
+constexpr int ACC = FFT_MAXN / NTH;  // model columns per thread
+
+// Inverse row transforms of z[b][t][row] for all t and the blend
+// out[b][row][x] = scale / M sum_t Re(A_t(row, x) z_t(row, x)), x < nx.
+// Grid (nz, B); TC terms transformed at a time.
+__global__ __launch_bounds__(NTH) void k_rows_inv_blend(SymGeo g, const float2 *__restrict__ z,
+                                                        int T, int TC, const float2 *__restrict__ A,
+                                                        float scale, float *__restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int n = g.mx, nz = g.nz, nx = g.nx;
+  float2 *tw = sm, *a = sm + n, *b = a + TC * n;
+  load_tw(tw, g.fx);
+  const int row = blockIdx.x;
+  const long long bv = blockIdx.y;
+  float acc[ACC];
+#pragma unroll
+  for (int i = 0; i < ACC; ++i) acc[i] = 0.0f;
+  for (int t0 = 0; t0 < T; t0 += TC) {
+    const int nl = min(TC, T - t0);
+    for (int e = threadIdx.x; e < nl * n; e += NTH) {
+      const int l = e / n, i = e - l * n;
+      a[l * n + i] = z[((bv * T + t0 + l) * nz + row) * (long long)n + i];
+    }
+    __syncthreads();
+    const float2 *res = fft_lines<true>(a, b, n, nl, g.fx, tw);
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) {
+      const int x = threadIdx.x + i * NTH;
+      if (x < nx) {
+        float s = acc[i];
+        for (int l = 0; l < nl; ++l) {
+          const float2 c = A[((long long)(t0 + l) * nz + row) * nx + x];
+          const float2 y = res[l * n + x];
+          s = fmaf(c.x, y.x, fmaf(-c.y, y.y, s));
+        }
+        acc[i] = s;
+      }
+    }
+    __syncthreads();
+  }
+  const float f = scale / ((float)g.mz * (float)g.mx);
+  float *o = out + (bv * nz + row) * (long long)nx;
+#pragma unroll
+  for (int i = 0; i < ACC; ++i) {
+    const int x = threadIdx.x + i * NTH;
+    if (x < nx) o[x] = acc[i] * f;
+  }
+}
+
+// Inverse row transforms of z[0][t][row] and demodulation by the sample
+// frequency: cols[t][row][x] = z_t e^{-i x.xi_t} / M (phase in FP64).  Grid
+// (nz, T).
+__global__ __launch_bounds__(NTH) void k_rows_inv_demod(SymGeo g, const float2 *__restrict__ z,
+                                                        float2 *__restrict__ cols) {
+  extern __shared__ float2 sm[];
+  const int n = g.mx, nz = g.nz, nx = g.nx;
+  float2 *tw = sm, *a = sm + n, *b = a + n;
+  load_tw(tw, g.fx);
+  const int row = blockIdx.x, t = blockIdx.y;
+  for (int i = threadIdx.x; i < n; i += NTH) a[i] = z[((long long)t * nz + row) * n + i];
+  __syncthreads();
+  const float2 *res = fft_lines<true>(a, b, n, 1, g.fx, tw);
+  const double inv_m = 1.0 / ((double)g.mz * g.mx);
+  for (int x = threadIdx.x; x < nx; x += NTH) {
+    const double ph = g.h * ((double)x * g.sx[t] + (double)row * g.sz[t]);
+    double s, c;
+    sincos(ph, &s, &c);
+    const double re = res[x].x, im = res[x].y;
+    cols[((long long)t * nz + row) * nx + x] =
+        make_float2((float)((re * c + im * s) * inv_m), (float)((im * c - re * s) * inv_m));
+  }
+}
+
+// ------------------------------------------------------------------- PDO
+
+__global__ void k_pdo_probe(SymGeo g, float *__restrict__ vp) {
+  const long long total = (long long)g.nz * g.nx;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int iz = (int)(e / g.nx), ix = (int)(e - (long long)iz * g.nx);
+    double s = 0.0;
+    for (int k = 0; k < g.r / 2; ++k) s += 2.0 * cos(g.h * ((double)ix * g.sx[k] + (double)iz * g.sz[k]));
+    vp[e] = (float)s;
+  }
+}
+
+__device__ inline void reps(int p, int m, double step, double *v, int *cnt) {
+  const int c = p <= m / 2 ? p : p - m;
+  v[0] = c * step;
+  *cnt = 1;
+  if ((m & 1) == 0 && p == m / 2) {
+    v[1] = -v[0];
+    *cnt = 2;
+  }
+}
+
+// Masks (nearest sample frequency, ties shared) and weights (rho / rho0 times
+// the angular cardinal function) for k = 1..r/2, averaged over the
+// representatives of each lattice point.  Either output may be null.
+__global__ void k_pdo_tables(SymGeo g, float2 *__restrict__ masks, float2 *__restrict__ wts) {
+  const long long plane = (long long)g.mz * g.mx;
+  const int r = g.r, hr = r / 2;
+  const double two_pi = 6.283185307179586476925;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < plane;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(e / g.mx), q = (int)(e - (long long)p * g.mx);
+    double zr[2], xr[2];
+    int nzr, nxr;
+    reps(p, g.mz, two_pi / (g.mz * g.h), zr, &nzr);
+    reps(q, g.mx, two_pi / (g.mx * g.h), xr, &nxr);
+    double mk[SYM_RMAX / 2], wk[SYM_RMAX / 2];
+    for (int k = 0; k < hr; ++k) mk[k] = wk[k] = 0.0;
+    for (int a = 0; a < nzr; ++a) {
+      for (int b = 0; b < nxr; ++b) {
+        const double xz = zr[a], xx = xr[b];
+        double d[SYM_RMAX];
+        double dmin = 1e300;
+        for (int k = 0; k < r; ++k) {
+          const double sx = k < hr ? g.sx[k] : -g.sx[k - hr];
+          const double sz = k < hr ? g.sz[k] : -g.sz[k - hr];
+          d[k] = (xx - sx) * (xx - sx) + (xz - sz) * (xz - sz);
+          dmin = fmin(dmin, d[k]);
+        }
+        const double lim = dmin + TIE * (xx * xx + xz * xz + g.rho0 * g.rho0);
+        int cnt = 0;
+        for (int k = 0; k < r; ++k) cnt += d[k] <= lim;
+        const double rho = sqrt(xx * xx + xz * xz);
+        const double th = atan2(xz, xx);
+        for (int k = 0; k < hr; ++k) {
+          if (d[k] <= lim) mk[k] += 1.0 / cnt;
+          const double dth = th - two_pi * (k + 1) / r;
+          double w = 1.0 + cos((r / 2) * dth);
+          for (int m = 1; m < r / 2; ++m) w += 2.0 * cos(m * dth);
+          wk[k] += rho / g.rho0 * w / r;
+        }
+      }
+    }
+    const double inv = 1.0 / (nzr * nxr);
+    for (int k = 0; k < hr; ++k) {
+      if (masks) masks[k * plane + e] = make_float2((float)(mk[k] * inv), 0.0f);
+      if (wts) wts[k * plane + e] = make_float2((float)(wk[k] * inv), 0.0f);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ PSF+
+
+struct PsfLat {  // centre lattice of the PSF method
+  int oz, ox, sz, sx, nzc, nxc, half, W, r;
+};
+
+// 1-D tent weights at index i: (c0, w0) and (c1, w1); c1 = c0 and w1 = 0 at
+// the clamped ends.
+__device__ inline void tent(int i, int o, int s, int n, int *c0, float *w0, int *c1, float *w1) {
+  if (n == 1 || i <= o) {
+    *c0 = *c1 = 0;
+    *w0 = 1.0f;
+    *w1 = 0.0f;
+  } else if (i >= o + (n - 1) * s) {
+    *c0 = *c1 = n - 1;
+    *w0 = 1.0f;
+    *w1 = 0.0f;
+  } else {
+    const int p = (i - o) / s;
+    const float t = (float)(i - o - p * s) / (float)s;
+    *c0 = p;
+    *c1 = p + 1;
+    *w0 = 1.0f - t;
+    *w1 = t;
+  }
+}
+
+// Real planes grid[j][mz][mx] holding kernel q_j at the wrapped offsets.
+__global__ void k_pp_scatter(int mz, int mx, int half, int W, const float *__restrict__ q, int rank,
+                             float *__restrict__ grid) {
+  const long long plane = (long long)mz * mx, total = plane * rank;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(e / plane);
+    const long long o = e - j * plane;
+    const int p = (int)(o / mx), c = (int)(o - (long long)p * mx);
+    const int dz = p <= half ? p : (p >= mz - half ? p - mz : 1 << 20);
+    const int dx = c <= half ? c : (c >= mx - half ? c - mx : 1 << 20);
+    float v = 0.0f;
+    if (dz <= half && dx <= half) v = q[(long long)j * W * W + (dz + half) * W + dx + half];
+    grid[e] = v;
+  }
+}
+
+// M_t = b_{2t} + i b_{2t+1}, b_j = conj(sum_d q_j(d) e^{-i d.xi}) = conj(Bq_j).
+__global__ void k_pp_pack(long long plane, const float2 *__restrict__ Bq, int rank, int T,
+                          float2 *__restrict__ M) {
+  const long long total = plane * T;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int t = (int)(e / plane);
+    const long long o = e - t * plane;
+    const float2 b0 = Bq[(long long)(2 * t) * plane + o];
+    float2 m = make_float2(b0.x, -b0.y);
+    if (2 * t + 1 < rank) {
+      const float2 b1 = Bq[(long long)(2 * t + 1) * plane + o];
+      m.x += b1.y;  // i conj(b1) = (b1.y, b1.x)
+      m.y += b1.x;
+    }
+    M[e] = m;
+  }
+}
+
+// sigma_j = sqrt(M mu_j) from the Gram eigenvalues mu (descending), the
+// kernel coefficients Qc[j][k] = U[k][j] / sigma_j (zero for dropped rows),
+// info[1] = kept rows, info[2 + j] = sigma_j.
+__global__ void k_pp_coefq(int rp, int rank, double M, const double *__restrict__ mu,
+                           const double *__restrict__ U, float *__restrict__ Qc,
+                           double *__restrict__ sigma, double *__restrict__ info) {
+  const double top = mu[0];
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < rank * rp; e += gridDim.x * blockDim.x) {
+    const int j = e / rp, k = e - j * rp;
+    const bool keep = top > 0.0 && mu[j] > 1e-12 * top;
+    const double s = keep ? sqrt(M * mu[j]) : 0.0;
+    Qc[e] = keep ? (float)(U[(long long)k * rp + j] / s) : 0.0f;
+    if (k == 0) {
+      sigma[j] = s;
+      info[2 + j] = s;
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    int kept = 0;
+    for (int j = 0; j < rank; ++j) kept += (top > 0.0 && mu[j] > 1e-12 * top);
+    info[1] = kept;
+  }
+}
+
+// Bc[j][k] = sum_d q_j(d) e^{i d.xi_k} for k < r/2 (FP64 phases and sums).
+// Grid (rank, r/2).
+__global__ __launch_bounds__(NTH) void k_pp_bc(SymGeo g, int half, const float *__restrict__ q,
+                                               double2 *__restrict__ Bc) {
+  const int j = blockIdx.x, k = blockIdx.y, hr = gridDim.y, W = 2 * half + 1;
+  double re = 0.0, im = 0.0;
+  for (int e = threadIdx.x; e < W * W; e += NTH) {
+    const int dz = e / W - half, dx = e % W - half;
+    const double ph = g.h * ((double)dx * g.sx[k] + (double)dz * g.sz[k]);
+    double s, c;
+    sincos(ph, &s, &c);
+    const double v = q[(long long)j * W * W + e];
+    re += v * c;
+    im += v * s;
+  }
+  __shared__ double rr[NTH], ii[NTH];
+  rr[threadIdx.x] = re;
+  ii[threadIdx.x] = im;
+  __syncthreads();
+  for (int w = NTH / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      rr[threadIdx.x] += rr[threadIdx.x + w];
+      ii[threadIdx.x] += ii[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) Bc[j * hr + k] = make_double2(rr[0], ii[0]);
+}
+
+// The Tikhonov normal equations: alpha = ||B[:, I_c]||^2 / ||B||^2 (= kept
+// orthonormal rows), G = Re(Bc Bc^H) + alpha I over all r columns (the
+// conjugate half doubles the real part), Ginv by Gauss-Jordan, and the
+// per-point maps
+//   Xr[k][l] = 2 sum_j Re Bc[j][k] Ginv[j][l],  Xi[k][l] = 2 sum_j Im Bc[j][k] Ginv[j][l],
+//   Z[c][l]  = alpha sum_j U[c][j] sigma_j Ginv[j][l]
+// so that a_l(x) = sum_k (Re C_k(x) Xr[k][l] + Im C_k(x) Xi[k][l])
+//               + sum_c w_c(x) Z[c][l].
+__global__ __launch_bounds__(NTH) void k_pp_solve(int rank, int hr, int rp,
+                                                  const double2 *__restrict__ Bc,
+                                                  const double *__restrict__ U,
+                                                  const double *__restrict__ sigma,
+                                                  float *__restrict__ Xr, float *__restrict__ Xi,
+                                                  float *__restrict__ Z, double *__restrict__ info) {
+  __shared__ double G[PP_RANK][2 * PP_RANK];
+  __shared__ double alpha_s;
+  if (threadIdx.x == 0) {
+    double nb = 0.0;
+    int kept = 0;
+    for (int j = 0; j < rank; ++j) {
+      kept += sigma[j] > 0.0;
+      for (int k = 0; k < hr; ++k) nb += 2.0 * (Bc[j * hr + k].x * Bc[j * hr + k].x + Bc[j * hr + k].y * Bc[j * hr + k].y);
+    }
+    const double alpha = kept > 0 ? nb / kept : 0.0;
+    alpha_s = alpha;
+    info[0] = alpha;
+    for (int j = 0; j < rank; ++j) {
+      for (int l = 0; l < rank; ++l) {
+        double s = 0.0;
+        for (int k = 0; k < hr; ++k) s += Bc[j * hr + k].x * Bc[l * hr + k].x + Bc[j * hr + k].y * Bc[l * hr + k].y;
+        G[j][l] = 2.0 * s + (j == l ? (alpha > 0.0 ? alpha : 1.0) : 0.0);
+        G[j][rank + l] = j == l ? 1.0 : 0.0;
+      }
+    }
+    // Gauss-Jordan with partial pivoting on [G | I]
+    for (int c = 0; c < rank; ++c) {
+      int piv = c;
+      for (int i = c + 1; i < rank; ++i)
+        if (fabs(G[i][c]) > fabs(G[piv][c])) piv = i;
+      if (piv != c)
+        for (int l = 0; l < 2 * rank; ++l) {
+          const double t = G[c][l];
+          G[c][l] = G[piv][l];
+          G[piv][l] = t;
+        }
+      const double d = 1.0 / G[c][c];
+      for (int l = 0; l < 2 * rank; ++l) G[c][l] *= d;
+      for (int i = 0; i < rank; ++i) {
+        if (i == c) continue;
+        const double f = G[i][c];
+        if (f != 0.0)
+          for (int l = 0; l < 2 * rank; ++l) G[i][l] -= f * G[c][l];
+      }
+    }
+  }
+  __syncthreads();
+  const double alpha = alpha_s;
+  // with alpha = 0 (no basis energy at the samples) the coefficients are A0
+  const double ya = alpha > 0.0 ? alpha : 1.0;
+  for (int e = threadIdx.x; e < hr * rank; e += NTH) {
+    const int k = e / rank, l = e - k * rank;
+    double sr = 0.0, si = 0.0;
+    if (alpha > 0.0)
+      for (int j = 0; j < rank; ++j) {
+        sr += Bc[j * hr + k].x * G[j][rank + l];
+        si += Bc[j * hr + k].y * G[j][rank + l];
+      }
+    Xr[e] = (float)(2.0 * sr);
+    Xi[e] = (float)(2.0 * si);
+  }
+  for (int e = threadIdx.x; e < rp * rank; e += NTH) {
+    const int c = e / rank, l = e - c * rank;
+    double s = 0.0;
+    for (int j = 0; j < rank; ++j) s += U[(long long)c * rp + j] * sigma[j] * G[j][rank + l];
+    Z[e] = (float)(ya * s);
+  }
+}
+
+// a_l(x) for every model cell, packed A_t = a_{2t} - i a_{2t+1}.
+__global__ __launch_bounds__(NTH) void k_pp_coef(int nz, int nx, PsfLat L, int rank, int hr,
+                                                 const float2 *__restrict__ cols,
+                                                 const float *__restrict__ Xr,
+                                                 const float *__restrict__ Xi,
+                                                 const float *__restrict__ Z,
+                                                 float2 *__restrict__ A) {
+  const long long plane = (long long)nz * nx;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < plane;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int iz = (int)(e / nx), ix = (int)(e - (long long)iz * nx);
+    int pz0, pz1, qx0, qx1;
+    float wz0, wz1, wx0, wx1;
+    tent(iz, L.oz, L.sz, L.nzc, &pz0, &wz0, &pz1, &wz1);
+    tent(ix, L.ox, L.sx, L.nxc, &qx0, &wx0, &qx1, &wx1);
+    const int c00 = pz0 * L.nxc + qx0, c01 = pz0 * L.nxc + qx1;
+    const int c10 = pz1 * L.nxc + qx0, c11 = pz1 * L.nxc + qx1;
+    const float w00 = wz0 * wx0, w01 = wz0 * wx1, w10 = wz1 * wx0, w11 = wz1 * wx1;
+    float a[PP_RANK];
+#pragma unroll
+    for (int l = 0; l < PP_RANK; ++l) a[l] = 0.0f;
+    for (int k = 0; k < hr; ++k) {
+      const float2 c = cols[k * plane + e];
+#pragma unroll
+      for (int l = 0; l < PP_RANK; ++l)
+        if (l < rank) a[l] = fmaf(c.x, Xr[k * rank + l], fmaf(c.y, Xi[k * rank + l], a[l]));
+    }
+#pragma unroll
+    for (int l = 0; l < PP_RANK; ++l) {
+      if (l < rank) {
+        float s = a[l];
+        s = fmaf(w00, Z[c00 * rank + l], s);
+        s = fmaf(w01, Z[c01 * rank + l], s);
+        s = fmaf(w10, Z[c10 * rank + l], s);
+        s = fmaf(w11, Z[c11 * rank + l], s);
+        a[l] = s;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < PP_RANK / 2; ++t) {
+      if (2 * t < rank)
+        A[t * plane + e] = make_float2(a[2 * t], 2 * t + 1 < rank ? -a[2 * t + 1] : 0.0f);
+    }
+  }
+}
+
+unsigned nblk(long long n) { return (unsigned)std::min<long long>((n + NTH - 1) / NTH, 16384); }
+
+}  // namespace
+}  // namespace fwi
+
+using namespace fwi;
+
+struct fwi_symbol {
+  fwi_symbol_grid gi{};
+  SymGeo g{};
+  std::vector<float2> host;  // twiddles of mx, then of mz
+  size_t off_tz = 0;         // float2 offset of the mz table
+  void *dev = nullptr;
+};
+
+namespace {
+
+#define SY_TRY(expr)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (expr);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return set_error(FWI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));     \
+  } while (0)
+
+template <class T>
+T *at_(void *base, size_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(base) + off);
+}
+
+size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
+
+bool factor(int n, Fft1 &f) {
+  f.n = n;
+  f.ns = 0;
+  int m = n;
+  const int rs[4] = {4, 2, 3, 5};
+  for (int R : rs) {
+    while (m % R == 0) {
+      if (f.ns == FFT_MAXST) return false;
+      f.radix[f.ns++] = R;
+      m /= R;
+    }
+  }
+  return m == 1;
+}
+
+int check_grid(const fwi_symbol_grid *g) {
+  if (!g) return set_error(FWI_EINVAL, "symbol grid is null");
+  if (g->nz < 1 || g->nx < 1 || g->nz > FFT_MAXN || g->nx > FFT_MAXN)
+    return set_error(FWI_EINVAL, "symbol grid: nz, nx must be in [1, 2048]");
+  if (g->mz < g->nz || g->mx < g->nx || g->mz > FFT_MAXN || g->mx > FFT_MAXN)
+    return set_error(FWI_EINVAL, "symbol grid: need nz <= mz <= 2048 and nx <= mx <= 2048");
+  Fft1 f;
+  if (!factor(g->mz, f) || !factor(g->mx, f))
+    return set_error(FWI_EINVAL, "symbol grid: mz and mx must have no prime factor above 5");
+  if (!(g->h > 0.0)) return set_error(FWI_EINVAL, "symbol grid: h must be positive");
+  if (g->r < 2 || g->r > SYM_RMAX || (g->r & 1))
+    return set_error(FWI_EINVAL, "symbol grid: r must be even, in [2, 16]");
+  if (!(g->rho0 > 0.0) || !std::isfinite(g->rho0))
+    return set_error(FWI_EINVAL, "symbol grid: rho0 must be positive");
+  return FWI_OK;
+}
+
+int check_bound(const fwi_symbol *s) {
+  if (!s) return set_error(FWI_EINVAL, "symbol object is null");
+  if (!s->dev) return set_error(FWI_EUNBOUND, "symbol object has no device block: call fwi_symbol_bind");
+  return FWI_OK;
+}
+
+// Column band width of the column passes (LDS: twiddles + two bands).
+int col_band(int mz) {
+  int C = (LDS_BUDGET / (int)sizeof(float2) - mz) / (2 * (mz + 1));
+  C = std::max(1, std::min(16, C));
+  int p = 1;
+  while (p * 2 <= C) p *= 2;
+  return p;
+}
+size_t col_lds(int mz, int C) { return sizeof(float2) * (mz + 2 * (size_t)C * (mz + 1)); }
+int row_terms(int mx) {
+  return std::max(1, std::min(4, (LDS_BUDGET / (int)sizeof(float2) / mx - 1) / 2));
+}
+size_t row_lds(int mx, int lines) { return sizeof(float2) * mx * (1 + 2 * (size_t)lines); }
+
+struct ApplyLayout {
+  size_t spec, rowt, z, total;
+};
+ApplyLayout apply_layout(const fwi_symbol_grid &g, int B, int T) {
+  ApplyLayout L{};
+  size_t off = 0;
+  L.spec = off; off += up256(sizeof(float2) * (size_t)B * g.mz * g.mx);
+  L.rowt = off; off += up256(sizeof(float2) * (size_t)B * g.nz * g.mx);
+  L.z = off; off += up256(sizeof(float2) * (size_t)B * T * g.nz * g.mx);
+  L.total = off;
+  return L;
+}
+
+// spec[b] = unnormalised forward 2-D DFT of the zero-padded real planes
+// in[b][rows][cols] (rows <= mz, cols <= mx).
+int forward(const fwi_symbol *s, const float *in, int rows, int cols, int B, float2 *rowt,
+            float2 *spec, hipStream_t st) {
+  const SymGeo &g = s->g;
+  hipLaunchKernelGGL(k_rows_fwd, dim3(rows, B), dim3(NTH), row_lds(g.mx, 1), st, g, in, rows, cols,
+                     rowt);
+  SY_TRY(hipGetLastError());
+  const int C = col_band(g.mz);
+  hipLaunchKernelGGL(k_cols_fwd, dim3((g.mx + C - 1) / C, B), dim3(NTH), col_lds(g.mz, C), st, g,
+                     rowt, rows, C, spec);
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+int inverse_cols(const fwi_symbol *s, const float2 *spec, const float2 *M, int T, int B, float2 *z,
+                 hipStream_t st) {
+  const SymGeo &g = s->g;
+  const int C = col_band(g.mz);
+  hipLaunchKernelGGL(k_cols_inv, dim3((g.mx + C - 1) / C, T, B), dim3(NTH), col_lds(g.mz, C), st, g,
+                     spec, M, T, C, z);
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwi_symbol_check(const fwi_symbol_grid *g) { return check_grid(g); }
+
+int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
+  if (!out) return set_error(FWI_EINVAL, "null argument");
+  *out = nullptr;
+  if (int rc = check_grid(g)) return rc;
+  fwi_symbol *s = new fwi_symbol;
+  s->gi = *g;
+  SymGeo &G = s->g;
+  G.nz = g->nz;
+  G.nx = g->nx;
+  G.mz = g->mz;
+  G.mx = g->mx;
+  G.r = g->r;
+  G.h = g->h;
+  G.rho0 = g->rho0;
+  factor(g->mz, G.fz);
+  factor(g->mx, G.fx);
+  for (int k = 0; k < g->r / 2; ++k) {
+    const double th = 2.0 * M_PI * (k + 1) / g->r;
+    G.sx[k] = g->rho0 * std::cos(th);
+    G.sz[k] = g->rho0 * std::sin(th);
+  }
+  s->host.resize((size_t)g->mx + g->mz);
+  for (int m = 0; m < g->mx; ++m) {
+    const double a = -2.0 * M_PI * m / g->mx;
+    s->host[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  s->off_tz = (size_t)g->mx;
+  for (int m = 0; m < g->mz; ++m) {
+    const double a = -2.0 * M_PI * m / g->mz;
+    s->host[s->off_tz + m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  *out = s;
+  return FWI_OK;
+}
+
+void fwi_symbol_destroy(fwi_symbol *s) { delete s; }
+
+int fwi_symbol_device_bytes(const fwi_symbol *s, size_t *bytes) {
+  if (!s || !bytes) return set_error(FWI_EINVAL, "null argument");
+  *bytes = sizeof(float2) * s->host.size();
+  return FWI_OK;
+}
+
+int fwi_symbol_bind(fwi_symbol *s, void *dev, size_t bytes, void *stream) {
+  if (!s || !dev) return set_error(FWI_EINVAL, "null argument");
+  if (bytes < sizeof(float2) * s->host.size()) return set_error(FWI_ENOMEM, "symbol device block too small");
+  if (reinterpret_cast<uintptr_t>(dev) & 255)
+    return set_error(FWI_EINVAL, "symbol device block must be 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SY_TRY(hipMemcpyAsync(dev, s->host.data(), sizeof(float2) * s->host.size(), hipMemcpyHostToDevice, st));
+  SY_TRY(hipStreamSynchronize(st));
+  s->dev = dev;
+  s->g.fx.tw = static_cast<const float2 *>(dev);
+  s->g.fz.tw = static_cast<const float2 *>(dev) + s->off_tz;
+  return FWI_OK;
+}
+
+int fwi_symbol_workspace_size(const fwi_symbol *s, int B, int T, size_t *bytes) {
+  if (!s || !bytes) return set_error(FWI_EINVAL, "null argument");
+  if (B < 1 || B > 1024 || T < 1 || T > 64) return set_error(FWI_EINVAL, "B must be in [1, 1024], T in [1, 64]");
+  *bytes = apply_layout(s->gi, B, T).total;
+  return FWI_OK;
+}
+
+int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float scale,
+                     const float *v, int B, float *out, void *ws, size_t ws_bytes, void *stream) {
+  if (int rc = check_bound(s)) return rc;
+  if (!A || !M || !v || !out || !ws) return set_error(FWI_EINVAL, "fwi_symbol_apply: null array");
+  if (B < 1 || B > 1024 || T < 1 || T > 64) return set_error(FWI_EINVAL, "fwi_symbol_apply: B must be in [1, 1024], T in [1, 64]");
+  if (v == out) return set_error(FWI_EINVAL, "fwi_symbol_apply: out must not alias v");
+  const ApplyLayout L = apply_layout(s->gi, B, T);
+  if (ws_bytes < L.total) return set_error(FWI_ENOMEM, "workspace too small: need " + std::to_string(L.total));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const SymGeo &g = s->g;
+  float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
+  if (int rc = forward(s, v, g.nz, g.nx, B, rowt, spec, st)) return rc;
+  if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, B, z, st)) return rc;
+  const int TC = std::min(T, row_terms(g.mx));
+  hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, B), dim3(NTH), row_lds(g.mx, TC), st, g, z, T, TC,
+                     reinterpret_cast<const float2 *>(A), scale, out);
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+int fwi_pdo_probe(fwi_symbol *s, float *vp, void *stream) {
+  if (!s || !vp) return set_error(FWI_EINVAL, "fwi_pdo_probe: null argument");
+  hipLaunchKernelGGL(k_pdo_probe, dim3(nblk((long long)s->g.nz * s->g.nx)), dim3(NTH), 0,
+                     static_cast<hipStream_t>(stream), s->g, vp);
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+static int pdo_tables(fwi_symbol *s, float *masks, float *wts, void *stream) {
+  hipLaunchKernelGGL(k_pdo_tables, dim3(nblk((long long)s->g.mz * s->g.mx)), dim3(NTH), 0,
+                     static_cast<hipStream_t>(stream), s->g, reinterpret_cast<float2 *>(masks),
+                     reinterpret_cast<float2 *>(wts));
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+int fwi_pdo_weights(fwi_symbol *s, float *M, void *stream) {
+  if (!s || !M) return set_error(FWI_EINVAL, "fwi_pdo_weights: null argument");
+  return pdo_tables(s, nullptr, M, stream);
+}
+
+int fwi_pdo_masks(fwi_symbol *s, float *masks, void *stream) {
+  if (!s || !masks) return set_error(FWI_EINVAL, "fwi_pdo_masks: null argument");
+  return pdo_tables(s, masks, nullptr, stream);
+}
+
+int fwi_pdo_workspace_size(const fwi_symbol *s, size_t *bytes) {
+  if (!s || !bytes) return set_error(FWI_EINVAL, "null argument");
+  const int hr = s->gi.r / 2;
+  *bytes = apply_layout(s->gi, 1, hr).total + up256(sizeof(float2) * (size_t)hr * s->gi.mz * s->gi.mx);
+  return FWI_OK;
+}
+
+int fwi_pdo_columns(fwi_symbol *s, const float *hvp, float *cols, void *ws, size_t ws_bytes,
+                    void *stream) {
+  if (int rc = check_bound(s)) return rc;
+  if (!hvp || !cols || !ws) return set_error(FWI_EINVAL, "fwi_pdo_columns: null array");
+  size_t need = 0;
+  fwi_pdo_workspace_size(s, &need);
+  if (ws_bytes < need) return set_error(FWI_ENOMEM, "workspace too small: need " + std::to_string(need));
+  const SymGeo &g = s->g;
+  const int hr = g.r / 2;
+  const ApplyLayout L = apply_layout(s->gi, 1, hr);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
+  float2 *masks = at_<float2>(ws, L.total);
+  if (int rc = pdo_tables(s, reinterpret_cast<float *>(masks), nullptr, stream)) return rc;
+  if (int rc = forward(s, hvp, g.nz, g.nx, 1, rowt, spec, st)) return rc;
+  if (int rc = inverse_cols(s, spec, masks, hr, 1, z, st)) return rc;
+  hipLaunchKernelGGL(k_rows_inv_demod, dim3(g.nz, hr), dim3(NTH), row_lds(g.mx, 1), st, g, z,
+                     reinterpret_cast<float2 *>(cols));
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+struct PpLayout {
+  size_t G, Z, w, Zs, part, sigma, Qc, q, grid, rowt, Bq, Bc, Xr, Xi, Zf, total;
+};
+
+PpLayout pp_layout(const fwi_symbol_grid &g, int rp, int W, int rank) {
+  PpLayout L{};
+  size_t off = 0;
+  const size_t plane = (size_t)g.mz * g.mx;
+  auto take = [&](size_t &f, size_t b) { f = off; off += up256(b); };
+  take(L.G, sizeof(double) * rp * rp);
+  take(L.Z, sizeof(double) * rp * rp);
+  take(L.w, sizeof(double) * rp);
+  take(L.Zs, sizeof(double) * rp * rp);
+  take(L.part, sizeof(double) * (size_t)nchunks((long long)W * W) * rp * rp);
+  take(L.sigma, sizeof(double) * rank);
+  take(L.Qc, sizeof(float) * rank * rp);
+  take(L.q, sizeof(float) * (size_t)rank * W * W);
+  take(L.grid, sizeof(float) * rank * plane);
+  take(L.rowt, sizeof(float2) * rank * plane);
+  take(L.Bq, sizeof(float2) * rank * plane);
+  take(L.Bc, sizeof(double2) * rank * (g.r / 2));
+  take(L.Xr, sizeof(float) * rank * (g.r / 2));
+  take(L.Xi, sizeof(float) * rank * (g.r / 2));
+  take(L.Zf, sizeof(float) * (size_t)rp * rank);
+  L.total = off;
+  return L;
+}
+
+int pp_check(const fwi_symbol *s, const fwi_psf_grid *pg, int rank) {
+  if (!s || !pg) return set_error(FWI_EINVAL, "null argument");
+  if (int rc = fwi_psf_check(pg)) return rc;
+  if (pg->nz != s->gi.nz || pg->nx != s->gi.nx)
+    return set_error(FWI_EINVAL, "PSF grid and symbol grid describe different models");
+  const int rp = pg->nzc * pg->nxc, W = 2 * pg->half + 1;
+  if (rp > EIG_KMAX) return set_error(FWI_EINVAL, "PSF+: at most 512 PSFs");
+  if (W > std::min(s->gi.mz, s->gi.mx)) return set_error(FWI_EINVAL, "PSF+: PSF window wider than the FFT grid");
+  if (rank < 1 || rank > std::min(rp, PP_RANK)) return set_error(FWI_EINVAL, "PSF+: rank must be in [1, min(r_psf, 32)]");
+  return FWI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fwi_psfplus_workspace_size(const fwi_symbol *s, const fwi_psf_grid *pg, int rank,
+                               size_t *bytes) {
+  if (!bytes) return set_error(FWI_EINVAL, "null argument");
+  if (int rc = pp_check(s, pg, rank)) return rc;
+  *bytes = pp_layout(s->gi, pg->nzc * pg->nxc, 2 * pg->half + 1, rank).total;
+  return FWI_OK;
+}
+
+int fwi_psfplus_build(fwi_symbol *s, const fwi_psf_grid *pg, const float *psf, const float *cols,
+                      int rank, float *A, float *M, double *info, void *ws, size_t ws_bytes,
+                      void *stream) {
+  if (int rc = pp_check(s, pg, rank)) return rc;
+  if (int rc = check_bound(s)) return rc;
+  if (!psf || !cols || !A || !M || !info || !ws) return set_error(FWI_EINVAL, "fwi_psfplus_build: null array");
+  const int rp = pg->nzc * pg->nxc, W = 2 * pg->half + 1, WW = W * W;
+  const PpLayout L = pp_layout(s->gi, rp, W, rank);
+  if (ws_bytes < L.total) return set_error(FWI_ENOMEM, "workspace too small: need " + std::to_string(L.total));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const SymGeo &g = s->g;
+  const int hr = g.r / 2, T = (rank + 1) / 2;
+  const long long plane = (long long)g.mz * g.mx;
+  // Gram matrix of the PSF windows (FP64) and its eigenpairs
+  {
+    Gemm gm = plain(rp, rp, WW);
+    gm.A = psf; gm.am = WW; gm.ak = 1;
+    gm.B = psf; gm.bk = 1; gm.bn = WW;
+    SY_TRY(gemm_long(gm, at_<double>(ws, L.part), at_<double>(ws, L.G), st));
+  }
+  SY_TRY(sym_eig(rp, at_<double>(ws, L.G), at_<double>(ws, L.Z), at_<double>(ws, L.w),
+                 at_<double>(ws, L.Zs), st));
+  hipLaunchKernelGGL(k_pp_coefq, dim3(nblk((long long)rank * rp)), dim3(NTH), 0, st, rp, rank,
+                     (double)plane, at_<double>(ws, L.w), at_<double>(ws, L.Zs), at_<float>(ws, L.Qc),
+                     at_<double>(ws, L.sigma), info);
+  SY_TRY(hipGetLastError());
+  // basis kernels q_j = sum_k U[k][j] p_k / sigma_j
+  {
+    Gemm gm = plain(rank, WW, rp);
+    gm.A = at_<float>(ws, L.Qc); gm.am = rp; gm.ak = 1;
+    gm.B = psf; gm.bk = WW; gm.bn = 1;
+    gm.C = at_<float>(ws, L.q); gm.cm = WW; gm.cn = 1;
+    SY_TRY(gemm(gm, 1, st));
+  }
+  // their symbols on the lattice, packed in pairs
+  hipLaunchKernelGGL(k_pp_scatter, dim3(nblk(plane * rank)), dim3(NTH), 0, st, g.mz, g.mx,
+                     pg->half, W, at_<float>(ws, L.q), rank, at_<float>(ws, L.grid));
+  SY_TRY(hipGetLastError());
+  if (int rc = forward(s, at_<float>(ws, L.grid), g.mz, g.mx, rank, at_<float2>(ws, L.rowt),
+                       at_<float2>(ws, L.Bq), st))
+    return rc;
+  hipLaunchKernelGGL(k_pp_pack, dim3(nblk(plane * T)), dim3(NTH), 0, st, plane,
+                     at_<float2>(ws, L.Bq), rank, T, reinterpret_cast<float2 *>(M));
+  SY_TRY(hipGetLastError());
+  // the basis at the sample frequencies, the normal equations, the coefficients
+  hipLaunchKernelGGL(k_pp_bc, dim3(rank, hr), dim3(NTH), 0, st, g, pg->half, at_<float>(ws, L.q),
+                     at_<double2>(ws, L.Bc));
+  SY_TRY(hipGetLastError());
+  hipLaunchKernelGGL(k_pp_solve, dim3(1), dim3(NTH), 0, st, rank, hr, rp, at_<double2>(ws, L.Bc),
+                     at_<double>(ws, L.Zs), at_<double>(ws, L.sigma), at_<float>(ws, L.Xr),
+                     at_<float>(ws, L.Xi), at_<float>(ws, L.Zf), info);
+  SY_TRY(hipGetLastError());
+  PsfLat lat{pg->oz, pg->ox, pg->sz, pg->sx, pg->nzc, pg->nxc, pg->half, W, rp};
+  hipLaunchKernelGGL(k_pp_coef, dim3(nblk((long long)g.nz * g.nx)), dim3(NTH), 0, st, g.nz, g.nx, lat,
+                     rank, hr, reinterpret_cast<const float2 *>(cols), at_<float>(ws, L.Xr),
+                     at_<float>(ws, L.Xi), at_<float>(ws, L.Zf), reinterpret_cast<float2 *>(A));
+  SY_TRY(hipGetLastError());
+  return FWI_OK;
+}
+
+}  // extern "C"

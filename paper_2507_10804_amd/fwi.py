@@ -1,6 +1,7 @@
-"""Thin ctypes binding of the C ABI in ``include/fwi.h`` (and of the PSF and
-low-rank entry points of ``include/fwi_psf.h`` and ``include/fwi_lowrank.h``,
-wrapped in :mod:`.psf` and :mod:`.lowrank`).
+"""Thin ctypes binding of the C ABI in ``include/fwi.h`` (and of the PSF,
+low-rank and symbol entry points of ``include/fwi_psf.h``,
+``include/fwi_lowrank.h`` and ``include/fwi_symbol.h``, wrapped in
+:mod:`.psf`, :mod:`.lowrank` and :mod:`.symbol`).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``libfwi_mi355x.so``.  PyTorch supplies device memory (plan block,
@@ -30,7 +31,11 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_psf_check", "fwi_psf_extract", "fwi_psf_apply", "fwi_misfit_grad_hvp",
            "fwi_prior_create", "fwi_prior_destroy", "fwi_prior_device_bytes", "fwi_prior_bind",
            "fwi_prior_workspace_size", "fwi_prior_apply", "fwi_lowrank_workspace_size",
-           "fwi_lowrank_range", "fwi_lowrank_project", "fwi_lowrank_apply"]
+           "fwi_lowrank_range", "fwi_lowrank_project", "fwi_lowrank_apply", "fwi_symbol_check",
+           "fwi_symbol_create", "fwi_symbol_destroy", "fwi_symbol_device_bytes",
+           "fwi_symbol_bind", "fwi_symbol_workspace_size", "fwi_symbol_apply", "fwi_pdo_probe",
+           "fwi_pdo_weights", "fwi_pdo_masks", "fwi_pdo_workspace_size", "fwi_pdo_columns",
+           "fwi_psfplus_workspace_size", "fwi_psfplus_build"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -100,6 +105,20 @@ def load_library(path: str = LIB_PATH):
             "fwi_lowrank_apply": ([P, I, P, P, I, P, I, P, P, Z, P], I),
             "fwi_psf_extract": ([P, P, P, P], I),
             "fwi_psf_apply": ([P, P, P, I, P, P], I),
+            "fwi_symbol_check": ([P], I),
+            "fwi_symbol_create": ([P, P], I),
+            "fwi_symbol_destroy": ([P], None),
+            "fwi_symbol_device_bytes": ([P, P], I),
+            "fwi_symbol_bind": ([P, P, Z, P], I),
+            "fwi_symbol_workspace_size": ([P, I, I, P], I),
+            "fwi_symbol_apply": ([P, I, P, P, ctypes.c_float, P, I, P, P, Z, P], I),
+            "fwi_pdo_probe": ([P, P, P], I),
+            "fwi_pdo_weights": ([P, P, P], I),
+            "fwi_pdo_masks": ([P, P, P], I),
+            "fwi_pdo_workspace_size": ([P, P], I),
+            "fwi_pdo_columns": ([P, P, P, P, Z, P], I),
+            "fwi_psfplus_workspace_size": ([P, P, I, P], I),
+            "fwi_psfplus_build": ([P, P, P, P, I, P, P, P, P, Z, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)

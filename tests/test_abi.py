@@ -120,3 +120,38 @@ def test_psf_grid_validation(lib):
         with pytest.raises(fwi.FwiError) as ei:
             gpsf.check(g)
         assert ei.value.code == -1
+
+
+def test_symbol_grid_validation(lib):
+    """Host-side checks of the FFT grid of the symbol approximations, and the
+    host tables of a symbol object (no kernel runs)."""
+    import ctypes
+
+    from paper_2507_10804_amd import symbol as gsym
+
+    good = [synth.symbol_grid(301, 921, 10.0, 31, r=8, rho0=0.02),
+            synth.SymbolGrid(1, 1, 1, 1, 1.0, 2, 1.0),
+            synth.SymbolGrid(7, 9, 2048, 1125, 0.5, 16, 3.0)]
+    for g in good:
+        gsym.check(g)
+    bad = [synth.SymbolGrid(10, 10, 9, 10, 1.0, 8, 1.0),      # FFT grid smaller than the model
+           synth.SymbolGrid(10, 10, 14, 10, 1.0, 8, 1.0),     # factor 7
+           synth.SymbolGrid(10, 10, 10, 4096, 1.0, 8, 1.0),   # longer than 2048
+           synth.SymbolGrid(10, 10, 10, 10, 0.0, 8, 1.0),     # spacing
+           synth.SymbolGrid(10, 10, 10, 10, 1.0, 7, 1.0),     # odd r
+           synth.SymbolGrid(10, 10, 10, 10, 1.0, 18, 1.0),    # too many directions
+           synth.SymbolGrid(10, 10, 10, 10, 1.0, 8, 0.0)]     # radius
+    for g in bad:
+        with pytest.raises(fwi.FwiError) as ei:
+            gsym.check(g)
+        assert ei.value.code == -1
+    gc = gsym._gridc(good[0])
+    h = ctypes.c_void_p()
+    assert lib.fwi_symbol_create(ctypes.byref(gc), ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    assert lib.fwi_symbol_device_bytes(h, ctypes.byref(n)) == 0
+    assert n.value == 8 * (good[0].mz + good[0].mx)
+    # unbound object: the compute entry points refuse before touching the GPU
+    assert lib.fwi_pdo_columns(h, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
+                               1 << 30, None) == -6
+    lib.fwi_symbol_destroy(h)

@@ -1,0 +1,261 @@
+"""PDO, PSF+ and the low-rank symbol apply on the GPU against the FP64 oracle
+(oracle/pdo.py), all through the C ABI of include/fwi_symbol.h.
+
+Tolerances: the library's transforms are FP32 (twiddles rounded from FP64),
+so an M-point 2-D transform carries ~log2(M) eps32 relative error; tables
+and results are compared in relative L2 at 1e-5 (apply, columns, weights).
+The separation masks are decisions (values 0, 1, 1/2, ... 1/r), taken in
+FP64 on both sides with the same tie tolerance: compared exactly.  PSF+
+goes through an SVD truncation and a least-squares solve; with a
+well-separated singular spectrum the approximation is compared at 1e-4.
+End to end through the wave Hessian (FP32 solves, ~1e-5) at 1e-3.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import pdo as D
+from oracle import psf as P
+from paper_2507_10804_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def crel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def dev(torch, a, dtype=None):
+    dtype = dtype or torch.float32
+    npdt = np.complex64 if dtype == torch.complex64 else np.float32
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=npdt), device="cuda")
+
+
+def host(x):
+    x = x.detach().cpu().numpy()
+    return x.astype(np.complex128 if np.iscomplexobj(x) else np.float64)
+
+
+def r32(a):
+    """Values as the device sees them (FP32 or complex64 rounding)."""
+    a = np.asarray(a)
+    return (a.astype(np.complex64) if np.iscomplexobj(a) else a.astype(np.float32)).astype(
+        np.complex128 if np.iscomplexobj(a) else np.float64)
+
+
+GRIDS = [
+    (37, 45, 48, 60, 8),       # factors 2, 3 and 4
+    (20, 33, 25, 36, 4),       # 5^2 columns
+    (1, 7, 1, 8, 2),           # one row, trivial column transforms
+    (13, 1, 15, 1, 6),         # one column
+    (301, 921, 360, 960, 8),   # the 921 x 301 model with a 31-cell padding
+]
+
+
+@pytest.mark.parametrize("shape", GRIDS)
+def test_apply_matches_oracle(shape):
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    nz, nx, mz, mx, r = shape
+    G = synth.SymbolGrid(nz, nx, mz, mx, 7.5, r, 0.05)
+    rng = np.random.default_rng(nz * 7 + nx)
+    T, B = 3, 2
+    A = r32(rng.standard_normal((T, nz, nx)) + 1j * rng.standard_normal((T, nz, nx)))
+    M = r32(rng.standard_normal((T, mz, mx)) + 1j * rng.standard_normal((T, mz, mx)))
+    v = r32(rng.standard_normal((B, nz, nx)))
+    say(f"case: fwi_symbol_apply {nz}x{nx} on {mz}x{mx}, T={T}, B={B}")
+    sym = S.Symbol(G)
+    got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 1.5,
+                         dev(torch, v)))
+    for b in range(B):
+        ref = 1.5 * D.symbol_apply(G, A, M, v[b])
+        e = crel(got[b], ref)
+        say(f"  vector {b}: rel-L2 {e:.2e}")
+        assert e < 1e-5
+
+
+def test_apply_many_terms_and_vectors():
+    """T above one LDS batch of terms, B > 1: every (vector, term) pair."""
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    G = synth.SymbolGrid(30, 50, 32, 54, 1.0, 8, 0.5)
+    rng = np.random.default_rng(11)
+    T, B = 9, 5
+    A = r32(rng.standard_normal((T, 30, 50)) + 1j * rng.standard_normal((T, 30, 50)))
+    M = r32(rng.standard_normal((T, 32, 54)) + 1j * rng.standard_normal((T, 32, 54)))
+    v = r32(rng.standard_normal((B, 30, 50)))
+    say("case: fwi_symbol_apply 30x50 on 32x54, T=9, B=5")
+    sym = S.Symbol(G)
+    got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 1.0,
+                         dev(torch, v)))
+    for b in range(B):
+        assert crel(got[b], D.symbol_apply(G, A, M, v[b])) < 1e-5
+
+
+PDO_GRIDS = [
+    synth.SymbolGrid(24, 24, 24, 24, 1.0, 4, 2 * np.pi * 6 / 24),   # boundary ties
+    synth.symbol_grid(40, 52, 5.0, 7, r=8, rho0=0.31),
+    synth.symbol_grid(35, 29, 3.0, 5, r=6, rho0=0.4),
+    synth.symbol_grid(301, 921, 10.0, 31, r=8,
+                      rho0=synth.probe_radius(20.0, 5500.0)),
+]
+
+
+@pytest.mark.parametrize("G", PDO_GRIDS, ids=lambda G: f"{G.nz}x{G.nx}r{G.r}")
+def test_pdo_tables_and_probe(G):
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    say(f"case: fwi_pdo_probe/masks/weights {G.nz}x{G.nx} on {G.mz}x{G.mx}, r={G.r}")
+    sym = S.Symbol(G)
+    vp = host(sym.pdo_probe())
+    ref = D.probe(G)
+    assert np.abs(vp - ref).max() < 4e-6 * G.r
+    m = host(sym.pdo_masks()).real
+    mo = D.masks(G)[:G.r // 2]
+    assert np.array_equal(m, mo.astype(np.float32).astype(np.float64)), "mask decisions differ"
+    w = host(sym.pdo_weights())
+    wo = D.weights(G)[:G.r // 2]
+    e = crel(w, wo)
+    say(f"  masks equal; weights rel-L2 {e:.2e}")
+    assert e < 1e-6 and np.abs(w.imag).max() == 0.0
+    del torch
+
+
+@pytest.mark.parametrize("G", PDO_GRIDS[1:], ids=lambda G: f"{G.nz}x{G.nx}r{G.r}")
+def test_pdo_columns_and_apply(G):
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    say(f"case: fwi_pdo_columns + apply {G.nz}x{G.nx} on {G.mz}x{G.mx}, r={G.r}")
+    rng = np.random.default_rng(G.nz + G.nx)
+    hvp = r32(synth.smooth_random((G.nz, G.nx), seed=G.nx, sigma=1.5) * D.probe(G))
+    sym = S.Symbol(G)
+    approx, cols = S.pdo(sym, dev(torch, hvp))
+    cg = host(cols)
+    co = D.columns(G, hvp)
+    for k in range(G.r // 2):
+        e = crel(cg[k], co[k])
+        assert e < 1e-5, f"column {k}: {e:.2e}"
+    v = r32(rng.standard_normal((2, G.nz, G.nx)))
+    got = host(approx(dev(torch, v)))
+    for b in range(2):
+        e = crel(got[b], D.pdo_apply(G, co, v[b]))
+        say(f"  vector {b}: apply rel-L2 {e:.2e}")
+        assert e < 1e-5
+
+
+def _psf_case(nz, nx, spacing, half, nk=10, seed=0):
+    """PSFs p_k = sum_j c_kj 2^-j kappa_j with random windows kappa_j and
+    coefficients c: singular values decay by ~2 per index, so a truncated
+    basis is well conditioned."""
+    pg = synth.psf_grid(nz, nx, spacing=spacing, half=half)
+    rng = np.random.default_rng(seed)
+    kap = rng.standard_normal((nk, pg.width, pg.width))
+    c = rng.standard_normal((pg.r, nk))
+    psf = np.einsum("kj,jzx->kzx", c * 0.5 ** np.arange(nk), kap)
+    return pg, r32(psf)
+
+
+@pytest.mark.parametrize("case", [(40, 52, 8, 3, 4), (64, 90, 16, 7, 6), (33, 47, 12, 5, 1)])
+def test_psf_plus_matches_oracle(case):
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    nz, nx, spacing, half, rank = case
+    pg, psf = _psf_case(nz, nx, spacing, half, seed=nz)
+    G = synth.symbol_grid(nz, nx, 4.0, half, r=8, rho0=0.35)
+    say(f"case: fwi_psfplus_build {nz}x{nx}, {pg.r} PSFs of width {pg.width}, rank {rank}")
+    rng = np.random.default_rng(3)
+    hvp = r32(synth.smooth_random((nz, nx), seed=5, sigma=1.0) * D.probe(G))
+    co = D.columns(G, hvp)
+    cols_half = r32(co[:4])
+    cols_full = np.concatenate([cols_half, np.conj(cols_half)])
+    A, B, alpha = D.psf_plus(G, pg, psf, cols_full, rank)
+    sig = np.linalg.svd(D.psf_rows(G, pg, psf).reshape(pg.r, -1), compute_uv=False)[:rank]
+    sym = S.Symbol(G)
+    approx, info = S.psf_plus(sym, pg, dev(torch, psf), dev(torch, cols_half, torch.complex64),
+                              rank)
+    info = host(info)
+    say(f"  alpha {info[0]:.6e} (oracle {alpha:.6e}), kept {int(info[1])}")
+    assert info[0] == pytest.approx(alpha, rel=1e-5)
+    assert int(info[1]) == rank
+    assert np.allclose(info[2:], sig, rtol=1e-5)
+    v = r32(rng.standard_normal((2, nz, nx)))
+    got = host(approx(dev(torch, v)))
+    for b in range(2):
+        e = crel(got[b], D.psf_plus_apply(G, A, B, v[b]))
+        say(f"  vector {b}: apply rel-L2 {e:.2e}")
+        assert e < 1e-4
+
+
+def test_psf_plus_full_rank_reproduces_psf_apply():
+    """Columns taken from the PSF approximation itself at full rank: PSF+
+    must return the PSF method's operator, here applied by the library's own
+    PSF kernel (an independent GPU code path)."""
+    import torch
+    from paper_2507_10804_amd import psf as gpsf
+    from paper_2507_10804_amd import symbol as S
+
+    pg, psf = _psf_case(24, 26, 8, 3, nk=12, seed=9)
+    G = synth.symbol_grid(24, 26, 1.0, pg.half, r=8, rho0=1.1)
+    say(f"case: PSF+ at full rank {pg.r} vs fwi_psf_apply, 24x26")
+    W = P.weights(pg)
+    Sc = D.rows_at(G, pg, psf, D.samples(G))
+    cols = r32(np.einsum("kzx,kc->czx", W, Sc)[:4])
+    sym = S.Symbol(G)
+    approx, info = S.psf_plus(sym, pg, dev(torch, psf), dev(torch, cols, torch.complex64), pg.r)
+    v = r32(np.random.default_rng(2).standard_normal((24, 26)))
+    got = host(approx(dev(torch, v)))
+    ref = host(gpsf.apply(pg, dev(torch, psf), dev(torch, v)))
+    e = crel(got, ref)
+    say(f"  rel-L2 {e:.2e} (kept {int(host(info)[1])})")
+    assert e < 1e-4
+
+
+def test_pdo_and_psf_plus_end_to_end_wave_hessian():
+    """Probe products through the wave Hessian on both sides (the oracle's
+    own FP64 solves), then the approximations applied to a smooth field."""
+    import torch
+    import oracle
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import psf as gpsf
+    from paper_2507_10804_amd import symbol as S
+
+    g, m_true, m_eval = synth.config_small()
+    m32 = r32(m_eval)
+    G = synth.symbol_grid(g.nz, g.nx, g.dx, 15, r=8,
+                          rho0=synth.probe_radius(2.5 * g.f0, float(m_eval.max())))
+    pg = synth.psf_grid(g.nz, g.nx, spacing=16, half=15)
+    rank = 6
+    say(f"case: PDO + PSF+ end to end, 128x128, 4 shots, nt={g.nt}, {pg.r} PSFs, rank {rank}")
+    # oracle
+    hvp_o = oracle.gn_hvp(g, m32, D.probe(G))
+    cols_o = D.columns(G, hvp_o)
+    combs = synth.psf_combs(pg)
+    psf_o = P.extract(pg, np.stack([oracle.gn_hvp(g, m32, c) for c in combs]))
+    A_o, B_o, alpha_o = D.psf_plus(G, pg, psf_o, cols_o, rank)
+    # library
+    plan = fwi.Plan(g)
+    md = dev(torch, m_eval)
+    sym = S.Symbol(G)
+    hvp = plan.gn_hvp(md, sym.pdo_probe()[None])[0]
+    pdo_op, cols = S.pdo(sym, hvp)
+    psf = gpsf.extract(pg, plan.gn_hvp(md, dev(torch, combs)))
+    pp_op, info = S.psf_plus(sym, pg, psf, cols, rank)
+    v = r32(synth.smooth_random((g.nz, g.nx), seed=4, sigma=3.0))
+    e1 = crel(host(pdo_op(dev(torch, v))), D.pdo_apply(G, cols_o, v))
+    e2 = crel(host(pp_op(dev(torch, v))), D.psf_plus_apply(G, A_o, B_o, v))
+    say(f"  PDO apply rel-L2 {e1:.2e}; PSF+ apply rel-L2 {e2:.2e}; alpha {host(info)[0]:.4e} "
+        f"(oracle {alpha_o:.4e})")
+    assert e1 < 1e-3 and e2 < 1e-3
