@@ -22,6 +22,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <string>
 #include <vector>
 
@@ -100,6 +101,16 @@ __device__ inline void dft(float2 *v) {
   }
 }
 
+// a / b for 0 <= a < 2^20 and 1 <= b <= 2^16, rb = 1/b in FP32: the estimate
+// is off by at most one and is corrected exactly (a runtime integer division
+// costs dozens of instructions, this five).
+__device__ inline int qdiv(int a, int b, float rb) {
+  int q = (int)((float)a * rb);
+  const int r = a - q * b;
+  q += (r >= b) - (r < 0);
+  return q;
+}
+
 // One Stockham stage of radix R over `nlines` lines of length n (pitch
 // apart): sub-transforms of length Ns become length Ns*R, output in natural
 // order after the last stage.
@@ -108,12 +119,13 @@ __device__ inline void stage(const float2 *src, float2 *dst, int pitch, int nlin
                              const float2 *tw) {
   const int nR = n / R;
   const int tstep = n / (Ns * R);
+  const float rnR = 1.0f / (float)nR, rNs = 1.0f / (float)Ns;
   for (int e = threadIdx.x; e < nlines * nR; e += blockDim.x) {
-    const int line = e / nR;
+    const int line = qdiv(e, nR, rnR);
     const int j = e - line * nR;
     const float2 *x = src + line * pitch;
     float2 *y = dst + line * pitch;
-    const int k = j % Ns;
+    const int k = j - qdiv(j, Ns, rNs) * Ns;
     float2 v[R];
 #pragma unroll
     for (int t = 0; t < R; ++t) v[t] = x[j + t * nR];
@@ -157,6 +169,26 @@ __device__ inline void load_tw(float2 *dst, const Fft1 &f) {
   for (int i = threadIdx.x; i < f.n; i += blockDim.x) dst[i] = f.tw[i];
 }
 
+// Copy `tot` elements global -> LDS as put(e, get(e)) with U independent
+// loads in flight per thread before the first LDS store: a plain loop would
+// wait out one memory latency per element.
+template <int U, class Get, class Put>
+__device__ inline void staged(int tot, Get get, Put put) {
+  for (int base = threadIdx.x; base < tot; base += U * NTH) {
+    float2 tmp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NTH;
+      tmp[u] = e < tot ? get(e) : make_float2(0.0f, 0.0f);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = base + u * NTH;
+      if (e < tot) put(e, tmp[u]);
+    }
+  }
+}
+
 // ------------------------------------------------------------- 2-D passes
 
 // Forward row transforms of B real planes in[b][rows][cols] (cols <= mx, zero
@@ -165,11 +197,12 @@ __global__ __launch_bounds__(NTH) void k_rows_fwd(SymGeo g, const float *__restr
                                                   int cols, float2 *__restrict__ out) {
   extern __shared__ float2 sm[];
   const int n = g.mx;
-  float2 *tw = sm, *a = sm + n, *b = a + n;
-  load_tw(tw, g.fx);
+  float2 *a = sm, *b = sm + n;
+  const float2 *tw = g.fx.tw;  // row tables outweigh a row: read through the cache
   const long long row = (long long)blockIdx.y * rows + blockIdx.x;
   const float *src = in + row * cols;
-  for (int i = threadIdx.x; i < n; i += NTH) a[i] = make_float2(i < cols ? src[i] : 0.0f, 0.0f);
+  staged<8>(n, [&](int i) { return make_float2(i < cols ? src[i] : 0.0f, 0.0f); },
+            [&](int i, float2 v) { a[i] = v; });
   __syncthreads();
   const float2 *res = fft_lines<false>(a, b, n, 1, g.fx, tw);
   float2 *dst = out + row * n;
@@ -179,54 +212,54 @@ __global__ __launch_bounds__(NTH) void k_rows_fwd(SymGeo g, const float *__restr
 // Forward column transforms: in[b][rows_in][mx] (rows beyond rows_in are
 // zero) to out[b][mz][mx].  A band of C adjacent columns per workgroup.
 __global__ __launch_bounds__(NTH) void k_cols_fwd(SymGeo g, const float2 *__restrict__ in,
-                                                  int rows_in, int C, float2 *__restrict__ out) {
+                                                  int rows_in, int cs, float2 *__restrict__ out) {
   extern __shared__ float2 sm[];
-  const int n = g.mz, pitch = n + 1, mx = g.mx;
+  const int C = 1 << cs, n = g.mz, pitch = n + 1, mx = g.mx;
   float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
   load_tw(tw, g.fz);
   const int col0 = blockIdx.x * C;
   const long long bz = blockIdx.y;
-  for (int e = threadIdx.x; e < n * C; e += NTH) {
-    const int i = e / C, c = e - i * C;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (i < rows_in && col0 + c < mx) v = in[(bz * rows_in + i) * mx + col0 + c];
-    a[c * pitch + i] = v;
-  }
+  staged<8>(n * C,
+            [&](int e) {
+              const int i = e >> cs, c = e & (C - 1);
+              return (i < rows_in && col0 + c < mx) ? in[(bz * rows_in + i) * mx + col0 + c]
+                                                    : make_float2(0.0f, 0.0f);
+            },
+            [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
   const float2 *res = fft_lines<false>(a, b, pitch, C, g.fz, tw);
   for (int e = threadIdx.x; e < n * C; e += NTH) {
-    const int i = e / C, c = e - i * C;
+    const int i = e >> cs, c = e & (C - 1);
     if (col0 + c < mx) out[(bz * n + i) * mx + col0 + c] = res[c * pitch + i];
   }
 }
 
 // Inverse column transforms of Mt[t] . spec[b], model rows stored:
-// z[b][t][nz][mx].  Grid (column bands, T, B).
+// z[b][t][nz][mx].  Grid (column bands, T, B); bands of C = 2^cs columns.
 __global__ __launch_bounds__(NTH) void k_cols_inv(SymGeo g, const float2 *__restrict__ spec,
-                                                  const float2 *__restrict__ Mt, int T, int C,
+                                                  const float2 *__restrict__ Mt, int T, int cs,
                                                   float2 *__restrict__ z) {
   extern __shared__ float2 sm[];
-  const int n = g.mz, pitch = n + 1, mx = g.mx;
+  const int C = 1 << cs, n = g.mz, pitch = n + 1, mx = g.mx;
   float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
   load_tw(tw, g.fz);
   const int col0 = blockIdx.x * C;
   const long long t = blockIdx.y, bv = blockIdx.z;
   const float2 *S = spec + bv * n * mx;
   const float2 *W = Mt + t * n * mx;
-  for (int e = threadIdx.x; e < n * C; e += NTH) {
-    const int i = e / C, c = e - i * C;
-    float2 v = make_float2(0.0f, 0.0f);
-    if (col0 + c < mx) {
-      const long long o = (long long)i * mx + col0 + c;
-      v = cmul(S[o], W[o]);
-    }
-    a[c * pitch + i] = v;
-  }
+  staged<8>(n * C,
+            [&](int e) {
+              const int i = e >> cs, c = e & (C - 1);
+              if (col0 + c >= mx) return make_float2(0.0f, 0.0f);
+              const long long o = (long long)i * mx + col0 + c;
+              return cmul(S[o], W[o]);
+            },
+            [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
   const float2 *res = fft_lines<true>(a, b, pitch, C, g.fz, tw);
   float2 *Z = z + (bv * T + t) * (long long)g.nz * mx;
   for (int e = threadIdx.x; e < g.nz * C; e += NTH) {
-    const int i = e / C, c = e - i * C;
+    const int i = e >> cs, c = e & (C - 1);
     if (col0 + c < mx) Z[(long long)i * mx + col0 + c] = res[c * pitch + i];
   }
 }
@@ -235,48 +268,70 @@ constexpr int ACC = FFT_MAXN / NTH;  // model columns per thread
 
 // Inverse row transforms of z[b][t][row] for all t and the blend
 // out[b][row][x] = scale / M sum_t Re(A_t(row, x) z_t(row, x)), x < nx.
-// Grid (nz, B); TC terms transformed at a time.
+// Grid (nz, ceil(B / BG)): a workgroup owns one row of BG vectors, so each
+// coefficient row A_t(row, :) is staged in LDS once for all of them; TC terms
+// are transformed at a time.
+constexpr int BGMAX = 4;
+
 __global__ __launch_bounds__(NTH) void k_rows_inv_blend(SymGeo g, const float2 *__restrict__ z,
-                                                        int T, int TC, const float2 *__restrict__ A,
-                                                        float scale, float *__restrict__ out) {
+                                                        int T, int TC, int B, int BG,
+                                                        const float2 *__restrict__ A, float scale,
+                                                        float *__restrict__ out) {
   extern __shared__ float2 sm[];
   const int n = g.mx, nz = g.nz, nx = g.nx;
-  float2 *tw = sm, *a = sm + n, *b = a + TC * n;
-  load_tw(tw, g.fx);
+  float2 *As = sm, *a = sm + TC * nx, *b = a + TC * n;
+  const float2 *tw = g.fx.tw;
   const int row = blockIdx.x;
-  const long long bv = blockIdx.y;
-  float acc[ACC];
+  const int b0 = blockIdx.y * BG;
+  const int nb = min(BG, B - b0);
+  float acc[BGMAX][ACC];
 #pragma unroll
-  for (int i = 0; i < ACC; ++i) acc[i] = 0.0f;
+  for (int v = 0; v < BGMAX; ++v)
+#pragma unroll
+    for (int i = 0; i < ACC; ++i) acc[v][i] = 0.0f;
   for (int t0 = 0; t0 < T; t0 += TC) {
     const int nl = min(TC, T - t0);
-    for (int e = threadIdx.x; e < nl * n; e += NTH) {
-      const int l = e / n, i = e - l * n;
-      a[l * n + i] = z[((bv * T + t0 + l) * nz + row) * (long long)n + i];
+    for (int l = 0; l < nl; ++l) {
+      const float2 *Ar = A + ((long long)(t0 + l) * nz + row) * nx;
+      staged<8>(nx, [&](int x) { return Ar[x]; }, [&](int x, float2 v) { As[l * nx + x] = v; });
     }
-    __syncthreads();
-    const float2 *res = fft_lines<true>(a, b, n, nl, g.fx, tw);
 #pragma unroll
-    for (int i = 0; i < ACC; ++i) {
-      const int x = threadIdx.x + i * NTH;
-      if (x < nx) {
-        float s = acc[i];
+    for (int v = 0; v < BGMAX; ++v) {
+      if (v < nb) {  // uniform over the workgroup
         for (int l = 0; l < nl; ++l) {
-          const float2 c = A[((long long)(t0 + l) * nz + row) * nx + x];
-          const float2 y = res[l * n + x];
-          s = fmaf(c.x, y.x, fmaf(-c.y, y.y, s));
+          const float2 *zr = z + (((long long)(b0 + v) * T + t0 + l) * nz + row) * n;
+          staged<8>(n, [&](int i) { return zr[i]; }, [&](int i, float2 w) { a[l * n + i] = w; });
         }
-        acc[i] = s;
+        __syncthreads();
+        const float2 *res = fft_lines<true>(a, b, n, nl, g.fx, tw);
+#pragma unroll
+        for (int i = 0; i < ACC; ++i) {
+          const int x = threadIdx.x + i * NTH;
+          if (x < nx) {
+            float s = acc[v][i];
+            for (int l = 0; l < nl; ++l) {
+              const float2 c = As[l * nx + x];
+              const float2 y = res[l * n + x];
+              s = fmaf(c.x, y.x, fmaf(-c.y, y.y, s));
+            }
+            acc[v][i] = s;
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
   }
   const float f = scale / ((float)g.mz * (float)g.mx);
-  float *o = out + (bv * nz + row) * (long long)nx;
 #pragma unroll
-  for (int i = 0; i < ACC; ++i) {
-    const int x = threadIdx.x + i * NTH;
-    if (x < nx) o[x] = acc[i] * f;
+  for (int v = 0; v < BGMAX; ++v) {
+    if (v < nb) {
+      float *o = out + ((long long)(b0 + v) * nz + row) * nx;
+#pragma unroll
+      for (int i = 0; i < ACC; ++i) {
+        const int x = threadIdx.x + i * NTH;
+        if (x < nx) o[x] = acc[v][i] * f;
+      }
+    }
   }
 }
 
@@ -287,10 +342,11 @@ __global__ __launch_bounds__(NTH) void k_rows_inv_demod(SymGeo g, const float2 *
                                                         float2 *__restrict__ cols) {
   extern __shared__ float2 sm[];
   const int n = g.mx, nz = g.nz, nx = g.nx;
-  float2 *tw = sm, *a = sm + n, *b = a + n;
-  load_tw(tw, g.fx);
+  float2 *a = sm, *b = sm + n;
+  const float2 *tw = g.fx.tw;
   const int row = blockIdx.x, t = blockIdx.y;
-  for (int i = threadIdx.x; i < n; i += NTH) a[i] = z[((long long)t * nz + row) * n + i];
+  const float2 *zr = z + ((long long)t * nz + row) * n;
+  staged<8>(n, [&](int i) { return zr[i]; }, [&](int i, float2 v) { a[i] = v; });
   __syncthreads();
   const float2 *res = fft_lines<true>(a, b, n, 1, g.fx, tw);
   const double inv_m = 1.0 / ((double)g.mz * g.mx);
@@ -629,6 +685,8 @@ struct fwi_symbol {
   std::vector<float2> host;  // twiddles of mx, then of mz
   size_t off_tz = 0;         // float2 offset of the mz table
   void *dev = nullptr;
+  size_t zchunk = (size_t)4 << 30;  // bytes of partial transforms per vector chunk
+  int bg = 4;                 // vectors per blend workgroup
 };
 
 namespace {
@@ -686,28 +744,42 @@ int check_bound(const fwi_symbol *s) {
 }
 
 // Column band width of the column passes (LDS: twiddles + two bands).
-int col_band(int mz) {
+int col_band(int mz) {  // log2 of the band width
   int C = (LDS_BUDGET / (int)sizeof(float2) - mz) / (2 * (mz + 1));
   C = std::max(1, std::min(16, C));
-  int p = 1;
-  while (p * 2 <= C) p *= 2;
-  return p;
+  int cs = 0;
+  while ((2 << cs) <= C) ++cs;
+  return cs;
 }
-size_t col_lds(int mz, int C) { return sizeof(float2) * (mz + 2 * (size_t)C * (mz + 1)); }
-int row_terms(int mx) {
-  return std::max(1, std::min(4, (LDS_BUDGET / (int)sizeof(float2) / mx - 1) / 2));
+size_t col_lds(int mz, int cs) { return sizeof(float2) * (mz + 2 * ((size_t)1 << cs) * (mz + 1)); }
+size_t row_lds(int mx) { return sizeof(float2) * 2 * (size_t)mx; }
+// Terms per blend step: LDS holds TC coefficient rows and two TC-line buffers.
+int blend_terms(int nx, int mx, int T) {
+  return std::max(1, std::min({4, T, (LDS_BUDGET / (int)sizeof(float2)) / (nx + 2 * mx)}));
 }
-size_t row_lds(int mx, int lines) { return sizeof(float2) * mx * (1 + 2 * (size_t)lines); }
+size_t blend_lds(int nx, int mx, int TC) { return sizeof(float2) * (size_t)TC * (nx + 2 * (size_t)mx); }
+
+// Vectors per chunk of an apply: the partial transforms of one chunk stay
+// within `zchunk` bytes (default 4 GiB: measured, smaller chunks that keep
+// them in the last-level cache lose more to lower parallelism than they gain).
+int apply_chunk(const fwi_symbol *s, int B, int T) {
+  const size_t per = sizeof(float2) * (size_t)T * s->gi.nz * s->gi.mx;
+  const int most = (int)std::max<size_t>(1, std::min<size_t>((size_t)B, s->zchunk / per));
+  const int chunks = (B + most - 1) / most;
+  return (B + chunks - 1) / chunks;  // balanced
+}
 
 struct ApplyLayout {
   size_t spec, rowt, z, total;
 };
-ApplyLayout apply_layout(const fwi_symbol_grid &g, int B, int T) {
+ApplyLayout apply_layout(const fwi_symbol *s, int B, int T) {
+  const fwi_symbol_grid &g = s->gi;
+  const int Bc = apply_chunk(s, B, T);
   ApplyLayout L{};
   size_t off = 0;
-  L.spec = off; off += up256(sizeof(float2) * (size_t)B * g.mz * g.mx);
-  L.rowt = off; off += up256(sizeof(float2) * (size_t)B * g.nz * g.mx);
-  L.z = off; off += up256(sizeof(float2) * (size_t)B * T * g.nz * g.mx);
+  L.spec = off; off += up256(sizeof(float2) * (size_t)Bc * g.mz * g.mx);
+  L.rowt = off; off += up256(sizeof(float2) * (size_t)Bc * g.nz * g.mx);
+  L.z = off; off += up256(sizeof(float2) * (size_t)Bc * T * g.nz * g.mx);
   L.total = off;
   return L;
 }
@@ -717,12 +789,12 @@ ApplyLayout apply_layout(const fwi_symbol_grid &g, int B, int T) {
 int forward(const fwi_symbol *s, const float *in, int rows, int cols, int B, float2 *rowt,
             float2 *spec, hipStream_t st) {
   const SymGeo &g = s->g;
-  hipLaunchKernelGGL(k_rows_fwd, dim3(rows, B), dim3(NTH), row_lds(g.mx, 1), st, g, in, rows, cols,
+  hipLaunchKernelGGL(k_rows_fwd, dim3(rows, B), dim3(NTH), row_lds(g.mx), st, g, in, rows, cols,
                      rowt);
   SY_TRY(hipGetLastError());
-  const int C = col_band(g.mz);
-  hipLaunchKernelGGL(k_cols_fwd, dim3((g.mx + C - 1) / C, B), dim3(NTH), col_lds(g.mz, C), st, g,
-                     rowt, rows, C, spec);
+  const int cs = col_band(g.mz), C = 1 << cs;
+  hipLaunchKernelGGL(k_cols_fwd, dim3((g.mx + C - 1) / C, B), dim3(NTH), col_lds(g.mz, cs), st, g,
+                     rowt, rows, cs, spec);
   SY_TRY(hipGetLastError());
   return FWI_OK;
 }
@@ -730,9 +802,9 @@ int forward(const fwi_symbol *s, const float *in, int rows, int cols, int B, flo
 int inverse_cols(const fwi_symbol *s, const float2 *spec, const float2 *M, int T, int B, float2 *z,
                  hipStream_t st) {
   const SymGeo &g = s->g;
-  const int C = col_band(g.mz);
-  hipLaunchKernelGGL(k_cols_inv, dim3((g.mx + C - 1) / C, T, B), dim3(NTH), col_lds(g.mz, C), st, g,
-                     spec, M, T, C, z);
+  const int cs = col_band(g.mz), C = 1 << cs;
+  hipLaunchKernelGGL(k_cols_inv, dim3((g.mx + C - 1) / C, T, B), dim3(NTH), col_lds(g.mz, cs), st, g,
+                     spec, M, T, cs, z);
   SY_TRY(hipGetLastError());
   return FWI_OK;
 }
@@ -749,6 +821,8 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   if (int rc = check_grid(g)) return rc;
   fwi_symbol *s = new fwi_symbol;
   s->gi = *g;
+  if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
+  if (const char *e = std::getenv("FWI_SYM_BG")) s->bg = std::max(1, std::min(BGMAX, std::atoi(e)));
   SymGeo &G = s->g;
   G.nz = g->nz;
   G.nx = g->nx;
@@ -803,7 +877,7 @@ int fwi_symbol_bind(fwi_symbol *s, void *dev, size_t bytes, void *stream) {
 int fwi_symbol_workspace_size(const fwi_symbol *s, int B, int T, size_t *bytes) {
   if (!s || !bytes) return set_error(FWI_EINVAL, "null argument");
   if (B < 1 || B > 1024 || T < 1 || T > 64) return set_error(FWI_EINVAL, "B must be in [1, 1024], T in [1, 64]");
-  *bytes = apply_layout(s->gi, B, T).total;
+  *bytes = apply_layout(s, B, T).total;
   return FWI_OK;
 }
 
@@ -813,17 +887,23 @@ int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float
   if (!A || !M || !v || !out || !ws) return set_error(FWI_EINVAL, "fwi_symbol_apply: null array");
   if (B < 1 || B > 1024 || T < 1 || T > 64) return set_error(FWI_EINVAL, "fwi_symbol_apply: B must be in [1, 1024], T in [1, 64]");
   if (v == out) return set_error(FWI_EINVAL, "fwi_symbol_apply: out must not alias v");
-  const ApplyLayout L = apply_layout(s->gi, B, T);
+  const ApplyLayout L = apply_layout(s, B, T);
   if (ws_bytes < L.total) return set_error(FWI_ENOMEM, "workspace too small: need " + std::to_string(L.total));
   hipStream_t st = static_cast<hipStream_t>(stream);
   const SymGeo &g = s->g;
   float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
-  if (int rc = forward(s, v, g.nz, g.nx, B, rowt, spec, st)) return rc;
-  if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, B, z, st)) return rc;
-  const int TC = std::min(T, row_terms(g.mx));
-  hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, B), dim3(NTH), row_lds(g.mx, TC), st, g, z, T, TC,
-                     reinterpret_cast<const float2 *>(A), scale, out);
-  SY_TRY(hipGetLastError());
+  const int Bc = apply_chunk(s, B, T);
+  const int TC = blend_terms(g.nx, g.mx, T);
+  const long long plane = (long long)g.nz * g.nx;
+  for (int b0 = 0; b0 < B; b0 += Bc) {
+    const int nb = std::min(Bc, B - b0);
+    if (int rc = forward(s, v + b0 * plane, g.nz, g.nx, nb, rowt, spec, st)) return rc;
+    if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, nb, z, st)) return rc;
+    hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(NTH),
+                       blend_lds(g.nx, g.mx, TC), st, g, z, T, TC, nb, s->bg,
+                       reinterpret_cast<const float2 *>(A), scale, out + b0 * plane);
+    SY_TRY(hipGetLastError());
+  }
   return FWI_OK;
 }
 
@@ -856,7 +936,7 @@ int fwi_pdo_masks(fwi_symbol *s, float *masks, void *stream) {
 int fwi_pdo_workspace_size(const fwi_symbol *s, size_t *bytes) {
   if (!s || !bytes) return set_error(FWI_EINVAL, "null argument");
   const int hr = s->gi.r / 2;
-  *bytes = apply_layout(s->gi, 1, hr).total + up256(sizeof(float2) * (size_t)hr * s->gi.mz * s->gi.mx);
+  *bytes = apply_layout(s, 1, hr).total + up256(sizeof(float2) * (size_t)hr * s->gi.mz * s->gi.mx);
   return FWI_OK;
 }
 
@@ -869,14 +949,14 @@ int fwi_pdo_columns(fwi_symbol *s, const float *hvp, float *cols, void *ws, size
   if (ws_bytes < need) return set_error(FWI_ENOMEM, "workspace too small: need " + std::to_string(need));
   const SymGeo &g = s->g;
   const int hr = g.r / 2;
-  const ApplyLayout L = apply_layout(s->gi, 1, hr);
+  const ApplyLayout L = apply_layout(s, 1, hr);
   hipStream_t st = static_cast<hipStream_t>(stream);
   float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
   float2 *masks = at_<float2>(ws, L.total);
   if (int rc = pdo_tables(s, reinterpret_cast<float *>(masks), nullptr, stream)) return rc;
   if (int rc = forward(s, hvp, g.nz, g.nx, 1, rowt, spec, st)) return rc;
   if (int rc = inverse_cols(s, spec, masks, hr, 1, z, st)) return rc;
-  hipLaunchKernelGGL(k_rows_inv_demod, dim3(g.nz, hr), dim3(NTH), row_lds(g.mx, 1), st, g, z,
+  hipLaunchKernelGGL(k_rows_inv_demod, dim3(g.nz, hr), dim3(NTH), row_lds(g.mx), st, g, z,
                      reinterpret_cast<float2 *>(cols));
   SY_TRY(hipGetLastError());
   return FWI_OK;
