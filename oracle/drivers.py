@@ -20,14 +20,16 @@ and the benchmark's CPU-baseline leg; shares no code with the HIP library.
     - any linear operator, e.g. the prior R^-1 or (H~_d + R)^-1 of a Hessian
       approximation (the paper's preconditioning), applied unscaled.
   Step length by backtracking from t = 1 (halving) until the Armijo
-  condition Phi(m + t p) <= Phi(m) + c1 t g^T p holds, c1 = 1e-4; the pair
+  condition Phi(m + t p) <= Phi(m) + c1 t g^T p holds, c1 = 1e-4 (a trial
+  whose Phi is not finite -- an unstable wave solve -- fails it); the pair
   is stored only if s^T y > 0.  (The paper does not state its line search;
   this is the reading.)
 * gpCN (Section 2.3, eq. "gpcn"): m' = m_map + sqrt(1 - beta^2)(m_k - m_map)
   + beta zeta with zeta ~ N(0, Gamma~_post), accepted when u_k < min(1,
   exp(Delta(m_k) - Delta(m'))), Delta(m) = Phi(m) - 1/2 ||m - m_map||^2
-  weighted by Gamma~_post^-1 = H~ (the approximate Hessian).  The white
-  noise behind zeta and the uniforms u_k are inputs.
+  weighted by Gamma~_post^-1 = H~ (the approximate Hessian); a proposal
+  with a non-finite Delta is rejected.  The white noise behind zeta and the
+  uniforms u_k are inputs.
 
 Pins (tests/test_oracle_drivers.py): the two-loop recursion equals the
 explicit BFGS inverse-Hessian update; L-BFGS with the exact inverse Hessian
@@ -91,7 +93,7 @@ def lbfgs(fg, m0, iters, h0=None, mem=5, c1=1e-4, max_backtrack=20):
             mn = m + t * p
             fn, gn = fg(mn)
             out["evals"] += 1
-            if fn <= f + c1 * t * gp or nb == max_backtrack:
+            if (math.isfinite(fn) and fn <= f + c1 * t * gp) or nb == max_backtrack:
                 break
             t *= 0.5
             nb += 1
@@ -126,7 +128,7 @@ def gpcn(phi, m_map, m0, beta, sample, hess, w, u):
     for wk, uk in zip(w, u):
         prop = m_map + c * (m - m_map) + beta * sample(wk)
         dp = delta(prop)
-        a = min(1.0, math.exp(min(dm - dp, 0.0)))
+        a = min(1.0, math.exp(min(dm - dp, 0.0))) if math.isfinite(dp) else 0.0
         if uk < a:
             m, dm = prop, dp
             acc.append(True)

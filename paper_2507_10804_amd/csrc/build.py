@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfwi_mi355x.so")
-SOURCES = ["fwi_kernels.hip", "fwi_psf.hip", "fwi_lowrank.hip", "fwi_symbol.hip", "fwi_api.cpp"]
+SOURCES = ["fwi_kernels.hip", "fwi_psf.hip", "fwi_lowrank.hip", "fwi_symbol.hip", "fwi_opt.hip",
+           "fwi_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

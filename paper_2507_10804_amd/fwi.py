@@ -1,7 +1,7 @@
 """Thin ctypes binding of the C ABI in ``include/fwi.h`` (and of the PSF,
-low-rank and symbol entry points of ``include/fwi_psf.h``,
-``include/fwi_lowrank.h`` and ``include/fwi_symbol.h``, wrapped in
-:mod:`.psf`, :mod:`.lowrank` and :mod:`.symbol`).
+low-rank, symbol and driver entry points of ``include/fwi_psf.h``,
+``include/fwi_lowrank.h``, ``include/fwi_symbol.h`` and ``include/fwi_opt.h``,
+wrapped in :mod:`.psf`, :mod:`.lowrank`, :mod:`.symbol` and :mod:`.drivers`).
 
 Argument marshalling only: every step of the computation runs in the HIP
 kernels of ``libfwi_mi355x.so``.  PyTorch supplies device memory (plan block,
@@ -35,7 +35,9 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_symbol_create", "fwi_symbol_destroy", "fwi_symbol_device_bytes",
            "fwi_symbol_bind", "fwi_symbol_workspace_size", "fwi_symbol_apply", "fwi_pdo_probe",
            "fwi_pdo_weights", "fwi_pdo_masks", "fwi_pdo_workspace_size", "fwi_pdo_columns",
-           "fwi_psfplus_workspace_size", "fwi_psfplus_build"]
+           "fwi_psfplus_workspace_size", "fwi_psfplus_build", "fwi_vec_workspace_size",
+           "fwi_vec_dot", "fwi_vec_update", "fwi_lbfgs_pair", "fwi_lbfgs_loop1",
+           "fwi_lbfgs_loop2"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 
 
@@ -68,6 +70,7 @@ def load_library(path: str = LIB_PATH):
             raise FwiError(-4, f"{path} not built: run __graft_entry__.build()")
         lib = ctypes.CDLL(path)
         P, I, Z, D = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+        L = ctypes.c_int64
         sig = {
             "fwi_abi_version": ([], I),
             "fwi_plan_create": ([P, P], I),
@@ -119,6 +122,12 @@ def load_library(path: str = LIB_PATH):
             "fwi_pdo_columns": ([P, P, P, P, Z, P], I),
             "fwi_psfplus_workspace_size": ([P, P, I, P], I),
             "fwi_psfplus_build": ([P, P, P, P, I, P, P, P, P, Z, P], I),
+            "fwi_vec_workspace_size": ([L, P], I),
+            "fwi_vec_dot": ([L, P, P, P, P, Z, P], I),
+            "fwi_vec_update": ([L, D, P, P, D, P, P], I),
+            "fwi_lbfgs_pair": ([L, P, P, P, P, P, Z, P], I),
+            "fwi_lbfgs_loop1": ([L, I, P, P, P, P, P, P, P, Z, P], I),
+            "fwi_lbfgs_loop2": ([L, I, P, P, P, P, P, P, P, Z, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)

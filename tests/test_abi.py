@@ -23,7 +23,7 @@ def lib():
 def declared_functions():
     text = "".join(open(h).read() for h in HEADERS)
     text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(fwi_[a-z_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(fwi_[a-z0-9_]+)\s*\(", text)))
 
 
 def test_header_matches_binding():
