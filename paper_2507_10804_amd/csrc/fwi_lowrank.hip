@@ -178,10 +178,16 @@ __global__ void k_prior_scale(const float *__restrict__ spec, long long plane, i
 
 // --------------------------------------------------------- small symmetric
 // Eigenpairs of the symmetric k x k FP64 matrix A (overwritten) by parallel
-// cyclic Jacobi (round-robin pairing; every round rotates k/2 disjoint
-// pairs: all row updates, then all column updates).  Outputs the eigenvalues
-// in descending order in w[k] and the matching eigenvectors as the columns
-// of Zs (k x k); Z is scratch.  At most max_sweeps sweeps.
+// cyclic Jacobi (round-robin pairing: every round rotates k/2 disjoint
+// pairs).  A round is A <- J^T A J with J block-diagonal over the pairs, so
+// every 2 x 2 block {p, q} x {p', q'} of A updates on its own as
+// R_pq A_block R_p'q'^T: one pass over A per round, no barrier between the
+// row and the column rotations.  The eigenvector matrix is kept transposed
+// (Z = V^T), which makes its update a row rotation with contiguous access.
+// Outputs the eigenvalues in descending order in w[k] and the matching
+// eigenvectors as the columns of Zs (k x k); Z is scratch.  At most
+// max_sweeps sweeps; stops when the off-diagonal Frobenius norm is below tol
+// times the whole norm.
 constexpr int EIG_T = 1024;
 
 __global__ __launch_bounds__(EIG_T) void k_symeig(int k, double *__restrict__ A,
@@ -190,48 +196,52 @@ __global__ __launch_bounds__(EIG_T) void k_symeig(int k, double *__restrict__ A,
                                                   double tol) {
   __shared__ double cs[EIG_KMAX / 2], sn[EIG_KMAX / 2];
   __shared__ int pp[EIG_KMAX / 2], qq[EIG_KMAX / 2];
-  __shared__ double red[EIG_T / 64];
+  __shared__ double red[EIG_T / 64], diag[EIG_KMAX];
   __shared__ int stop, perm[EIG_KMAX];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = EIG_T / 64;
   const int n = k + (k & 1);  // even count; index k is a placeholder when k is odd
   const int half = n / 2;
-  for (int e = tid; e < k * k; e += EIG_T) {
-    Z[e] = (e / k == e % k) ? 1.0 : 0.0;
-    const int i = e / k, j = e % k;
-    if (i < j) {  // exact symmetry of the input
-      const double s = 0.5 * (A[i * k + j] + A[j * k + i]);
-      A[i * k + j] = s;
-      A[j * k + i] = s;
+  for (int i = wave; i < k; i += NW) {
+    for (int j = lane; j < k; j += 64) {
+      Z[i * k + j] = i == j ? 1.0 : 0.0;
+      if (i < j) {  // exact symmetry of the input
+        const double sy = 0.5 * (A[i * k + j] + A[j * k + i]);
+        A[i * k + j] = sy;
+        A[j * k + i] = sy;
+      }
     }
   }
   __syncthreads();
   for (int sweep = 0; sweep < max_sweeps; ++sweep) {
     double off = 0.0, tot = 0.0;
-    for (int e = tid; e < k * k; e += EIG_T) {
-      const double a = A[e] * A[e];
-      tot += a;
-      if (e / k != e % k) off += a;
+    for (int i = wave; i < k; i += NW) {
+      for (int j = lane; j < k; j += 64) {
+        const double a = A[i * k + j] * A[i * k + j];
+        tot += a;
+        if (i != j) off += a;
+      }
     }
     for (int o = 32; o > 0; o >>= 1) {
       off += __shfl_down(off, o, 64);
       tot += __shfl_down(tot, o, 64);
     }
-    if (tid % 64 == 0) red[tid / 64] = off;
+    if (lane == 0) red[wave] = off;
     __syncthreads();
     if (tid == 0) {
-      double s = 0.0;
-      for (int q = 0; q < EIG_T / 64; ++q) s += red[q];
-      red[0] = s;
+      double sum = 0.0;
+      for (int q = 0; q < NW; ++q) sum += red[q];
+      red[0] = sum;
     }
     __syncthreads();
     const double offs = red[0];
     __syncthreads();
-    if (tid % 64 == 0) red[tid / 64] = tot;
+    if (lane == 0) red[wave] = tot;
     __syncthreads();
     if (tid == 0) {
-      double s = 0.0;
-      for (int q = 0; q < EIG_T / 64; ++q) s += red[q];
-      stop = (offs <= tol * tol * s) ? 1 : 0;
+      double sum = 0.0;
+      for (int q = 0; q < NW; ++q) sum += red[q];
+      stop = (offs <= tol * tol * sum) ? 1 : 0;
     }
     __syncthreads();
     if (stop) break;
@@ -240,7 +250,7 @@ __global__ __launch_bounds__(EIG_T) void k_symeig(int k, double *__restrict__ A,
         auto pos = [&](int x) { return x == 0 ? 0 : (x - 1 + round) % (n - 1) + 1; };
         int p = pos(tid), q = pos(n - 1 - tid);
         if (p > q) { const int t = p; p = q; q = t; }
-        double c = 1.0, s = 0.0;
+        double c = 1.0, sr = 0.0;
         if (q < k) {
           const double apq = A[p * k + q];
           if (apq != 0.0) {
@@ -250,55 +260,96 @@ __global__ __launch_bounds__(EIG_T) void k_symeig(int k, double *__restrict__ A,
                                  ? (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau))
                                  : 0.5 / tau;
             c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
+            sr = t * c;
           }
         }
         pp[tid] = p;
-        qq[tid] = q < k ? q : p;  // placeholder pair: identity rotation
+        qq[tid] = q < k ? q : -1;  // placeholder partner: a 1-wide block
         cs[tid] = c;
-        sn[tid] = q < k ? s : 0.0;
+        sn[tid] = q < k ? sr : 0.0;
       }
       __syncthreads();
-      for (int e = tid; e < half * k; e += EIG_T) {  // rows p, q of A
-        const int pr = e / k, j = e - pr * k;
-        const int p = pp[pr], q = qq[pr];
-        if (p == q) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[p * k + j], aq = A[q * k + j];
-        A[p * k + j] = c * ap - s * aq;
-        A[q * k + j] = s * ap + c * aq;
+      // A: the 2 x 2 blocks (pair r rows, pair u columns); 32 lanes per r.
+      // A thread issues the loads of UB blocks before their arithmetic, so a
+      // round costs a few memory round trips instead of one per block.
+      constexpr int UB = 4;
+      for (int r = tid >> 5; r < half; r += EIG_T >> 5) {
+        const int p = pp[r], q = qq[r];
+        const double c = cs[r], sr = sn[r];
+        for (int u0 = tid & 31; u0 < half; u0 += 32 * UB) {
+          double a00[UB], a01[UB], a10[UB], a11[UB];
+#pragma unroll
+          for (int i = 0; i < UB; ++i) {
+            const int u = u0 + 32 * i;
+            if (u < half) {
+              const int pu = pp[u], qu = qq[u];
+              a00[i] = A[p * k + pu];
+              a01[i] = qu >= 0 ? A[p * k + qu] : 0.0;
+              a10[i] = q >= 0 ? A[q * k + pu] : 0.0;
+              a11[i] = (q >= 0 && qu >= 0) ? A[q * k + qu] : 0.0;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < UB; ++i) {
+            const int u = u0 + 32 * i;
+            if (u < half) {
+              const int pu = pp[u], qu = qq[u];
+              const double cu = cs[u], su = sn[u];
+              const double b00 = c * a00[i] - sr * a10[i], b01 = c * a01[i] - sr * a11[i];
+              const double b10 = sr * a00[i] + c * a10[i], b11 = sr * a01[i] + c * a11[i];
+              A[p * k + pu] = b00 * cu - b01 * su;
+              if (qu >= 0) A[p * k + qu] = b00 * su + b01 * cu;
+              if (q >= 0) {
+                A[q * k + pu] = b10 * cu - b11 * su;
+                if (qu >= 0) A[q * k + qu] = b10 * su + b11 * cu;
+              }
+            }
+          }
+        }
       }
-      __syncthreads();
-      for (int e = tid; e < half * k; e += EIG_T) {  // columns p, q of A and Z
-        const int pr = e / k, j = e - pr * k;
-        const int p = pp[pr], q = qq[pr];
-        if (p == q) continue;
-        const double c = cs[pr], s = sn[pr];
-        const double ap = A[j * k + p], aq = A[j * k + q];
-        A[j * k + p] = c * ap - s * aq;
-        A[j * k + q] = s * ap + c * aq;
-        const double zp = Z[j * k + p], zq = Z[j * k + q];
-        Z[j * k + p] = c * zp - s * zq;
-        Z[j * k + q] = s * zp + c * zq;
+      // Z = V^T: rows p, q rotate like the rows of A (loads batched likewise)
+      for (int r = wave; r < half; r += NW) {
+        const int p = pp[r], q = qq[r];
+        if (q < 0) continue;
+        const double c = cs[r], sr = sn[r];
+        for (int j0 = lane; j0 < k; j0 += 64 * UB) {
+          double zp[UB], zq[UB];
+#pragma unroll
+          for (int i = 0; i < UB; ++i) {
+            const int j = j0 + 64 * i;
+            if (j < k) {
+              zp[i] = Z[p * k + j];
+              zq[i] = Z[q * k + j];
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < UB; ++i) {
+            const int j = j0 + 64 * i;
+            if (j < k) {
+              Z[p * k + j] = c * zp[i] - sr * zq[i];
+              Z[q * k + j] = sr * zp[i] + c * zq[i];
+            }
+          }
+        }
       }
       __syncthreads();
     }
   }
-  if (tid == 0) {  // order by descending eigenvalue (stable selection)
-    for (int i = 0; i < k; ++i) perm[i] = i;
-    for (int i = 0; i < k; ++i) {
-      int best = i;
-      for (int j = i + 1; j < k; ++j)
-        if (A[perm[j] * k + perm[j]] > A[perm[best] * k + perm[best]]) best = j;
-      const int t = perm[i]; perm[i] = perm[best]; perm[best] = t;
-    }
+  // order by descending eigenvalue: stable rank of each diagonal entry
+  for (int i = tid; i < k; i += EIG_T) diag[i] = A[i * k + i];
+  __syncthreads();
+  for (int i = tid; i < k; i += EIG_T) {
+    const double d = diag[i];
+    int rank = 0;
+    for (int j = 0; j < k; ++j) rank += (diag[j] > d) || (diag[j] == d && j < i);
+    perm[rank] = i;
   }
   __syncthreads();
-  for (int e = tid; e < k * k; e += EIG_T) {
-    const int i = e / k, j = e % k;
-    Zs[i * k + j] = Z[i * k + perm[j]];
+  for (int j = wave; j < k; j += NW) {
+    const int src = perm[j];
+    for (int i = lane; i < k; i += 64) Zs[i * k + j] = Z[src * k + i];
   }
-  for (int i = tid; i < k; i += EIG_T) w[i] = A[perm[i] * k + perm[i]];
+  for (int i = tid; i < k; i += EIG_T) w[i] = diag[perm[i]];
 }
 
 // Orthonormalising transform from the eigenpairs (w descending, columns of Zs)
