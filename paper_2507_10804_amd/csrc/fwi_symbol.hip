@@ -34,6 +34,8 @@ constexpr int FFT_MAXST = 12;
 constexpr int SYM_RMAX = 16;   // PDO directions
 constexpr int PP_RANK = 32;    // PSF+ rank
 constexpr int NTH = 256;
+constexpr int CNT = 512;  // threads of the column passes (8 waves per band)
+constexpr int BNT = 512;  // threads of the blend pass
 constexpr int LDS_BUDGET = 65536;
 constexpr double TIE = 1e-9;   // relative distance tolerance of the separation
 
@@ -165,6 +167,85 @@ __device__ float2 *fft_lines(float2 *a, float2 *b, int pitch, int nlines, const 
   return a;
 }
 
+// The stages of one line run by one wavefront alone: lanes stride over the
+// butterflies, and a stage's LDS writes are ordered before the next stage's
+// reads by a wavefront fence (a wavefront issues its LDS operations in order;
+// no workgroup barrier is needed).  Returns the buffer holding the result.
+template <bool INV>
+__device__ float2 *fft_wave(float2 *a, float2 *b, const Fft1 &f, const float2 *tw) {
+  const int lane = threadIdx.x & 63;
+  int Ns = 1;
+  for (int s = 0; s < f.ns; ++s) {
+    const int R = f.radix[s];
+    const int nR = f.n / R, tstep = f.n / (Ns * R);
+    const float rNs = 1.0f / (float)Ns;
+    for (int j = lane; j < nR; j += 64) {
+      const int k = j - qdiv(j, Ns, rNs) * Ns;
+      const int base = (j - k) * R + k;
+      float2 v[5];
+      if (R == 4) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = a[j + t * nR];
+        if (Ns > 1)
+#pragma unroll
+          for (int t = 1; t < 4; ++t) {
+            float2 w = tw[k * t * tstep];
+            if (INV) w.y = -w.y;
+            v[t] = cmul(v[t], w);
+          }
+        dft<4, INV>(v);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) b[base + t * Ns] = v[t];
+      } else if (R == 2) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) v[t] = a[j + t * nR];
+        if (Ns > 1) {
+          float2 w = tw[k * tstep];
+          if (INV) w.y = -w.y;
+          v[1] = cmul(v[1], w);
+        }
+        dft<2, INV>(v);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) b[base + t * Ns] = v[t];
+      } else if (R == 3) {
+#pragma unroll
+        for (int t = 0; t < 3; ++t) v[t] = a[j + t * nR];
+        if (Ns > 1)
+#pragma unroll
+          for (int t = 1; t < 3; ++t) {
+            float2 w = tw[k * t * tstep];
+            if (INV) w.y = -w.y;
+            v[t] = cmul(v[t], w);
+          }
+        dft<3, INV>(v);
+#pragma unroll
+        for (int t = 0; t < 3; ++t) b[base + t * Ns] = v[t];
+      } else {
+#pragma unroll
+        for (int t = 0; t < 5; ++t) v[t] = a[j + t * nR];
+        if (Ns > 1)
+#pragma unroll
+          for (int t = 1; t < 5; ++t) {
+            float2 w = tw[k * t * tstep];
+            if (INV) w.y = -w.y;
+            v[t] = cmul(v[t], w);
+          }
+        dft<5, INV>(v);
+#pragma unroll
+        for (int t = 0; t < 5; ++t) b[base + t * Ns] = v[t];
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float2 *t = a;
+    a = b;
+    b = t;
+    Ns *= R;
+  }
+  return a;
+}
+
 __device__ inline void load_tw(float2 *dst, const Fft1 &f) {
   for (int i = threadIdx.x; i < f.n; i += blockDim.x) dst[i] = f.tw[i];
 }
@@ -172,24 +253,49 @@ __device__ inline void load_tw(float2 *dst, const Fft1 &f) {
 // Copy `tot` elements global -> LDS as put(e, get(e)) with U independent
 // loads in flight per thread before the first LDS store: a plain loop would
 // wait out one memory latency per element.
-template <int U, class Get, class Put>
+template <int U, int NT = NTH, class Get, class Put>
 __device__ inline void staged(int tot, Get get, Put put) {
-  for (int base = threadIdx.x; base < tot; base += U * NTH) {
+  for (int base = threadIdx.x; base < tot; base += U * NT) {
     float2 tmp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = base + u * NTH;
+      const int e = base + u * NT;
       tmp[u] = e < tot ? get(e) : make_float2(0.0f, 0.0f);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = base + u * NTH;
+      const int e = base + u * NT;
       if (e < tot) put(e, tmp[u]);
     }
   }
 }
 
 // ------------------------------------------------------------- 2-D passes
+
+// The C lines of a column band: one wavefront per line when the band has as
+// many lines as the workgroup has wavefronts (then no workgroup barrier
+// between stages), else all threads share every stage.  Ends with a
+// workgroup barrier either way; returns the result buffer.
+template <bool INV>
+__device__ const float2 *cols_fft(float2 *a, float2 *b, int pitch, int C, const Fft1 &f,
+                                  const float2 *tw) {
+  if (C == CNT / 64) {
+    const int w = threadIdx.x >> 6;
+    const float2 *r = fft_wave<INV>(a + w * pitch, b + w * pitch, f, tw);
+    __syncthreads();
+    return r - w * pitch;  // the same buffer for every line (same stage count)
+  }
+  return fft_lines<INV>(a, b, pitch, C, f, tw);
+}
+
+// Column band of a workgroup: consecutive workgroup ids go round-robin to the
+// 8 XCDs (each with its own L2), so ids are remapped to give every XCD a
+// contiguous run of bands -- neighbouring bands share 128-byte lines.
+__device__ inline int xcd_band(int id, int nbands) {
+  const int per = (nbands + 7) / 8;
+  const int band = (id & 7) * per + (id >> 3);
+  return band < nbands ? band : -1;
+}
 
 // Forward row transforms of B real planes in[b][rows][cols] (cols <= mx, zero
 // beyond): out[b][rows][mx].  One row per workgroup.
@@ -211,15 +317,17 @@ __global__ __launch_bounds__(NTH) void k_rows_fwd(SymGeo g, const float *__restr
 
 // Forward column transforms: in[b][rows_in][mx] (rows beyond rows_in are
 // zero) to out[b][mz][mx].  A band of C adjacent columns per workgroup.
-__global__ __launch_bounds__(NTH) void k_cols_fwd(SymGeo g, const float2 *__restrict__ in,
+__global__ __launch_bounds__(CNT) void k_cols_fwd(SymGeo g, const float2 *__restrict__ in,
                                                   int rows_in, int cs, float2 *__restrict__ out) {
   extern __shared__ float2 sm[];
   const int C = 1 << cs, n = g.mz, pitch = n + 1, mx = g.mx;
   float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
+  const int band = xcd_band(blockIdx.x, (mx + C - 1) >> cs);
+  if (band < 0) return;  // grid padding (whole workgroup, before any barrier)
   load_tw(tw, g.fz);
-  const int col0 = blockIdx.x * C;
+  const int col0 = band * C;
   const long long bz = blockIdx.y;
-  staged<8>(n * C,
+  staged<8, CNT>(n * C,
             [&](int e) {
               const int i = e >> cs, c = e & (C - 1);
               return (i < rows_in && col0 + c < mx) ? in[(bz * rows_in + i) * mx + col0 + c]
@@ -227,8 +335,8 @@ __global__ __launch_bounds__(NTH) void k_cols_fwd(SymGeo g, const float2 *__rest
             },
             [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
-  const float2 *res = fft_lines<false>(a, b, pitch, C, g.fz, tw);
-  for (int e = threadIdx.x; e < n * C; e += NTH) {
+  const float2 *res = cols_fft<false>(a, b, pitch, C, g.fz, tw);
+  for (int e = threadIdx.x; e < n * C; e += CNT) {
     const int i = e >> cs, c = e & (C - 1);
     if (col0 + c < mx) out[(bz * n + i) * mx + col0 + c] = res[c * pitch + i];
   }
@@ -236,18 +344,20 @@ __global__ __launch_bounds__(NTH) void k_cols_fwd(SymGeo g, const float2 *__rest
 
 // Inverse column transforms of Mt[t] . spec[b], model rows stored:
 // z[b][t][nz][mx].  Grid (column bands, T, B); bands of C = 2^cs columns.
-__global__ __launch_bounds__(NTH) void k_cols_inv(SymGeo g, const float2 *__restrict__ spec,
+__global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__restrict__ spec,
                                                   const float2 *__restrict__ Mt, int T, int cs,
                                                   float2 *__restrict__ z) {
   extern __shared__ float2 sm[];
   const int C = 1 << cs, n = g.mz, pitch = n + 1, mx = g.mx;
   float2 *tw = sm, *a = sm + n, *b = a + C * pitch;
+  const int band = xcd_band(blockIdx.x, (mx + C - 1) >> cs);
+  if (band < 0) return;  // grid padding (whole workgroup, before any barrier)
   load_tw(tw, g.fz);
-  const int col0 = blockIdx.x * C;
+  const int col0 = band * C;
   const long long t = blockIdx.y, bv = blockIdx.z;
   const float2 *S = spec + bv * n * mx;
   const float2 *W = Mt + t * n * mx;
-  staged<8>(n * C,
+  staged<4, CNT>(n * C,
             [&](int e) {
               const int i = e >> cs, c = e & (C - 1);
               if (col0 + c >= mx) return make_float2(0.0f, 0.0f);
@@ -256,15 +366,15 @@ __global__ __launch_bounds__(NTH) void k_cols_inv(SymGeo g, const float2 *__rest
             },
             [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
-  const float2 *res = fft_lines<true>(a, b, pitch, C, g.fz, tw);
+  const float2 *res = cols_fft<true>(a, b, pitch, C, g.fz, tw);
   float2 *Z = z + (bv * T + t) * (long long)g.nz * mx;
-  for (int e = threadIdx.x; e < g.nz * C; e += NTH) {
+  for (int e = threadIdx.x; e < g.nz * C; e += CNT) {
     const int i = e >> cs, c = e & (C - 1);
     if (col0 + c < mx) Z[(long long)i * mx + col0 + c] = res[c * pitch + i];
   }
 }
 
-constexpr int ACC = FFT_MAXN / NTH;  // model columns per thread
+constexpr int ACC = FFT_MAXN / BNT;  // model columns per thread of the blend
 
 // Inverse row transforms of z[b][t][row] for all t and the blend
 // out[b][row][x] = scale / M sum_t Re(A_t(row, x) z_t(row, x)), x < nx.
@@ -273,7 +383,7 @@ constexpr int ACC = FFT_MAXN / NTH;  // model columns per thread
 // are transformed at a time.
 constexpr int BGMAX = 4;
 
-__global__ __launch_bounds__(NTH) void k_rows_inv_blend(SymGeo g, const float2 *__restrict__ z,
+__global__ __launch_bounds__(BNT) void k_rows_inv_blend(SymGeo g, const float2 *__restrict__ z,
                                                         int T, int TC, int B, int BG,
                                                         const float2 *__restrict__ A, float scale,
                                                         float *__restrict__ out) {
@@ -293,20 +403,20 @@ __global__ __launch_bounds__(NTH) void k_rows_inv_blend(SymGeo g, const float2 *
     const int nl = min(TC, T - t0);
     for (int l = 0; l < nl; ++l) {
       const float2 *Ar = A + ((long long)(t0 + l) * nz + row) * nx;
-      staged<8>(nx, [&](int x) { return Ar[x]; }, [&](int x, float2 v) { As[l * nx + x] = v; });
+      staged<4, BNT>(nx, [&](int x) { return Ar[x]; }, [&](int x, float2 v) { As[l * nx + x] = v; });
     }
 #pragma unroll
     for (int v = 0; v < BGMAX; ++v) {
       if (v < nb) {  // uniform over the workgroup
         for (int l = 0; l < nl; ++l) {
           const float2 *zr = z + (((long long)(b0 + v) * T + t0 + l) * nz + row) * n;
-          staged<8>(n, [&](int i) { return zr[i]; }, [&](int i, float2 w) { a[l * n + i] = w; });
+          staged<4, BNT>(n, [&](int i) { return zr[i]; }, [&](int i, float2 w) { a[l * n + i] = w; });
         }
         __syncthreads();
         const float2 *res = fft_lines<true>(a, b, n, nl, g.fx, tw);
 #pragma unroll
         for (int i = 0; i < ACC; ++i) {
-          const int x = threadIdx.x + i * NTH;
+          const int x = threadIdx.x + i * BNT;
           if (x < nx) {
             float s = acc[v][i];
             for (int l = 0; l < nl; ++l) {
@@ -328,7 +438,7 @@ __global__ __launch_bounds__(NTH) void k_rows_inv_blend(SymGeo g, const float2 *
       float *o = out + ((long long)(b0 + v) * nz + row) * nx;
 #pragma unroll
       for (int i = 0; i < ACC; ++i) {
-        const int x = threadIdx.x + i * NTH;
+        const int x = threadIdx.x + i * BNT;
         if (x < nx) o[x] = acc[v][i] * f;
       }
     }
@@ -751,6 +861,8 @@ int col_band(int mz) {  // log2 of the band width
   while ((2 << cs) <= C) ++cs;
   return cs;
 }
+// Workgroups of a column pass: the bands, padded to a multiple of the 8 XCDs.
+unsigned band_grid(int mx, int C) { return (unsigned)(8 * (((mx + C - 1) / C + 7) / 8)); }
 size_t col_lds(int mz, int cs) { return sizeof(float2) * (mz + 2 * ((size_t)1 << cs) * (mz + 1)); }
 size_t row_lds(int mx) { return sizeof(float2) * 2 * (size_t)mx; }
 // Terms per blend step: LDS holds TC coefficient rows and two TC-line buffers.
@@ -793,7 +905,7 @@ int forward(const fwi_symbol *s, const float *in, int rows, int cols, int B, flo
                      rowt);
   SY_TRY(hipGetLastError());
   const int cs = col_band(g.mz), C = 1 << cs;
-  hipLaunchKernelGGL(k_cols_fwd, dim3((g.mx + C - 1) / C, B), dim3(NTH), col_lds(g.mz, cs), st, g,
+  hipLaunchKernelGGL(k_cols_fwd, dim3(band_grid(g.mx, C), B), dim3(CNT), col_lds(g.mz, cs), st, g,
                      rowt, rows, cs, spec);
   SY_TRY(hipGetLastError());
   return FWI_OK;
@@ -803,7 +915,7 @@ int inverse_cols(const fwi_symbol *s, const float2 *spec, const float2 *M, int T
                  hipStream_t st) {
   const SymGeo &g = s->g;
   const int cs = col_band(g.mz), C = 1 << cs;
-  hipLaunchKernelGGL(k_cols_inv, dim3((g.mx + C - 1) / C, T, B), dim3(NTH), col_lds(g.mz, cs), st, g,
+  hipLaunchKernelGGL(k_cols_inv, dim3(band_grid(g.mx, C), T, B), dim3(CNT), col_lds(g.mz, cs), st, g,
                      spec, M, T, cs, z);
   SY_TRY(hipGetLastError());
   return FWI_OK;
@@ -899,7 +1011,7 @@ int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float
     const int nb = std::min(Bc, B - b0);
     if (int rc = forward(s, v + b0 * plane, g.nz, g.nx, nb, rowt, spec, st)) return rc;
     if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, nb, z, st)) return rc;
-    hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(NTH),
+    hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(BNT),
                        blend_lds(g.nx, g.mx, TC), st, g, z, T, TC, nb, s->bg,
                        reinterpret_cast<const float2 *>(A), scale, out + b0 * plane);
     SY_TRY(hipGetLastError());
