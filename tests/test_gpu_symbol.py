@@ -259,3 +259,40 @@ def test_pdo_and_psf_plus_end_to_end_wave_hessian():
     say(f"  PDO apply rel-L2 {e1:.2e}; PSF+ apply rel-L2 {e2:.2e}; alpha {host(info)[0]:.4e} "
         f"(oracle {alpha_o:.4e})")
     assert e1 < 1e-3 and e2 < 1e-3
+
+
+def test_psf_plus_full_size():
+    """The workload's sizes: 261 PSFs with 63 x 63 windows on the 921 x 301
+    model, 360 x 960 FFT grid, rank 16 (the bench's configuration), from
+    synthetic PSFs with a decaying singular spectrum and the oracle's PDO
+    columns of a synthetic H v_p; the oracle's complex SVD of the
+    261 x 345,600 row matrix against the library's Gram route."""
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    pg = synth.psf_grid(301, 921)
+    G = synth.symbol_grid(301, 921, 10.0, pg.half, r=8, rho0=synth.probe_radius(20.0, 5500.0))
+    rank = 16
+    rng = np.random.default_rng(31)
+    nk = 24
+    kap = rng.standard_normal((nk, pg.width, pg.width))
+    c = rng.standard_normal((pg.r, nk))
+    psf = r32(np.einsum("kj,jzx->kzx", c * 0.7 ** np.arange(nk), kap))
+    say(f"case: fwi_psfplus_build full size, {pg.r} PSFs of width {pg.width}, rank {rank}, "
+        f"{G.mz}x{G.mx} FFT grid")
+    hvp = r32(synth.smooth_random((301, 921), seed=7, sigma=2.0) * D.probe(G))
+    cols_half = r32(D.columns(G, hvp)[:4])
+    A, B, alpha = D.psf_plus(G, pg, psf, np.concatenate([cols_half, np.conj(cols_half)]), rank)
+    sig = np.linalg.svd(D.psf_rows(G, pg, psf).reshape(pg.r, -1), compute_uv=False)[:rank]
+    sym = S.Symbol(G)
+    approx, info = S.psf_plus(sym, pg, dev(torch, psf), dev(torch, cols_half, torch.complex64),
+                              rank)
+    info = host(info)
+    say(f"  alpha {info[0]:.6e} (oracle {alpha:.6e}); sigma_16 {info[1 + rank]:.6e} "
+        f"(oracle {sig[-1]:.6e})")
+    assert info[0] == pytest.approx(alpha, rel=1e-5)
+    assert np.allclose(info[2:], sig, rtol=1e-5)
+    v = r32(rng.standard_normal((301, 921)))
+    e = crel(host(approx(dev(torch, v))), D.psf_plus_apply(G, A, B, v))
+    say(f"  apply rel-L2 {e:.2e}")
+    assert e < 1e-4
