@@ -52,6 +52,8 @@ struct SymGeo {
   double sx[SYM_RMAX / 2], sz[SYM_RMAX / 2];  // xi_k for k = 1..r/2
 };
 
+typedef float f2v __attribute__((ext_vector_type(2)));  // for the non-temporal builtins
+
 __device__ inline float2 cmul(float2 a, float2 b) {
   return make_float2(fmaf(a.x, b.x, -a.y * b.y), fmaf(a.x, b.y, a.y * b.x));
 }
@@ -367,10 +369,16 @@ __global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__rest
             [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
   const float2 *res = cols_fft<true>(a, b, pitch, C, g.fz, tw);
-  float2 *Z = z + (bv * T + t) * (long long)g.nz * mx;
+  // streaming stores: the partial transforms are read once, by the next pass;
+  // allocating them in L2 would evict the table and spectrum bands that the
+  // other vectors' and terms' workgroups re-read
+  f2v *Z = reinterpret_cast<f2v *>(z + (bv * T + t) * (long long)g.nz * mx);
   for (int e = threadIdx.x; e < g.nz * C; e += CNT) {
     const int i = e >> cs, c = e & (C - 1);
-    if (col0 + c < mx) Z[(long long)i * mx + col0 + c] = res[c * pitch + i];
+    if (col0 + c < mx) {
+      const float2 r = res[c * pitch + i];
+      __builtin_nontemporal_store(f2v{r.x, r.y}, Z + (long long)i * mx + col0 + c);
+    }
   }
 }
 
