@@ -383,7 +383,8 @@ def lowrank_bench(args):
     torch.cuda.synchronize()
     t_build = time.perf_counter() - t0
     nseg = (g.nt - 1 + plan.K - 1) // plan.K
-    kern = _kernel_table(plan, 1, None)
+    a1, a2 = algorithmic_bytes_hvp(g, k, nseg), algorithmic_bytes_hvp(g, lr.kept, nseg)
+    kern = _kernel_table(plan, 1, {kind: a1[kind] + a2[kind] for kind in a1})
     plan.profile(False)
     plan.release_workspaces()
     del omega
@@ -418,11 +419,9 @@ def lowrank_bench(args):
            "eigenvalues": {"first": float(lam[0]), "tenth": float(lam[9]),
                            "last": float(lam[-1])},
            "kernels": {n: {kk: vv for kk, vv in v.items()} for n, v in kern.items()},
-           "roofline": {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": None, "traffic": None,
-                        "avg_launch_us": kern[dom]["avg_us"],
-                        "note": "the Hessian products dominate; their kernels' roofline is the "
-                                "default mode's"}}
+           "roofline": _roofline_from(kern, dom, "the two batches of Hessian products "
+                                                 "dominate; algorithmic bytes per launch of "
+                                                 "those two calls")}
     if not args.no_cpu_baseline:
         base = cpu_baseline(g, m_eval, synth.smooth_random((g.nz, g.nx), seed=1),
                             min(16, len(os.sched_getaffinity(0))), args.cpu_nt)
@@ -589,7 +588,8 @@ def map_bench(args):
     torch.cuda.synchronize()
     t_lbfgs = time.perf_counter() - t0
     evals = post.evals
-    kern = _kernel_table(plan, evals, None)
+    nseg = (g.nt - 1 + plan.K - 1) // plan.K
+    kern = _kernel_table(plan, evals, algorithmic_bytes_grad(g, nseg))
     plan.profile(False)
     log(f"map: low-rank r={r} in {t_lr:.1f} s; {args.steps} L-BFGS iterations, {evals} "
         f"evaluations, {t_lbfgs:.1f} s; Phi {hist['phi'][0]:.4e} -> {hist['phi'][-1]:.4e}; "
@@ -623,11 +623,10 @@ def map_bench(args):
            "lowrank_build_s": t_lr, "gpcn_steps_per_s": nsteps / t_gpcn,
            "gpcn_accepted": int(sum(acc)), "gpcn_steps": nsteps,
            "kernels": kern,
-           "roofline": {"bound": "hbm", "kernel": dom, "achieved": None, "peak": HBM_PEAK_GBS,
-                        "unit": "GB/s", "frac": None, "traffic": None,
-                        "avg_launch_us": kern[dom]["avg_us"],
-                        "note": "the wave solves of the objective dominate; their kernels' "
-                                "roofline is the default mode's"}}
+           "roofline": _roofline_from(kern, dom, "the misfit + gradient solves dominate; "
+                                                 "algorithmic bytes per launch of one "
+                                                 "evaluation (forward with checkpoints, "
+                                                 "recompute, one adjoint)")}
     if not args.no_cpu_baseline:
         import oracle
         from oracle import drivers as Dr
@@ -649,6 +648,27 @@ def map_bench(args):
                                          f"scaled by shot-steps and by the GPU run's "
                                          f"{per_iter:.1f} evaluations per iteration"}
     print(json.dumps(out), flush=True)
+
+
+def algorithmic_bytes_grad(g, nseg):
+    """Algorithmic bytes of one misfit + gradient call per kernel kind:
+    forward (gathering the data, storing checkpoints) and the segment
+    recompute on the forward kernel, one adjoint (see algorithmic_bytes)."""
+    full = algorithmic_bytes(g, 0, nseg, None, fused=False)
+    nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
+    rec = (g.nt - 1) * (4 * nzp * nxp * (3 * g.ns + 1) + 4 * g.ns * nzp * nxp)
+    adj1 = g.nt * (12 * nzp * nxp * g.ns + 4 * g.ns * g.nr) + (g.nt - 1) * (
+        4 * nzp * nxp * g.ns + 8 * nzp * nxp + 16 * nzp * nxp)
+    return {0: full[0] - rec, 2: adj1}
+
+
+def _roofline_from(kern, dom, note):
+    k = kern[dom]
+    ach = k.get("achieved_gbs")
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": None if ach is None else ach / HBM_PEAK_GBS, "traffic": None,
+            "alg_bytes_per_launch": k.get("alg_bytes_per_launch"), "avg_launch_us": k["avg_us"],
+            "note": note}
 
 
 def algorithmic_bytes_hvp(g, B, nseg):
