@@ -805,6 +805,7 @@ struct fwi_symbol {
   void *dev = nullptr;
   size_t zchunk = (size_t)4 << 30;  // bytes of partial transforms per vector chunk
   int bg = 4;                 // vectors per blend workgroup
+  int tc = 0;                 // terms per blend step (0: as many as LDS allows, at most 4)
 };
 
 namespace {
@@ -943,6 +944,7 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   s->gi = *g;
   if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
   if (const char *e = std::getenv("FWI_SYM_BG")) s->bg = std::max(1, std::min(BGMAX, std::atoi(e)));
+  if (const char *e = std::getenv("FWI_SYM_TC")) s->tc = std::max(0, std::min(4, std::atoi(e)));
   SymGeo &G = s->g;
   G.nz = g->nz;
   G.nx = g->nx;
@@ -1013,7 +1015,7 @@ int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float
   const SymGeo &g = s->g;
   float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
   const int Bc = apply_chunk(s, B, T);
-  const int TC = blend_terms(g.nx, g.mx, T);
+  const int TC = s->tc ? std::min(s->tc, blend_terms(g.nx, g.mx, T)) : blend_terms(g.nx, g.mx, T);
   const long long plane = (long long)g.nz * g.nx;
   for (int b0 = 0; b0 < B; b0 += Bc) {
     const int nb = std::min(Bc, B - b0);
