@@ -155,3 +155,40 @@ def test_symbol_grid_validation(lib):
     assert lib.fwi_pdo_columns(h, ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16),
                                1 << 30, None) == -6
     lib.fwi_symbol_destroy(h)
+
+
+def test_psfplus_and_vector_validation(lib):
+    """Argument checks of the PSF+ and driver entry points, all taken before
+    any device work (no GPU needed)."""
+    import ctypes
+
+    from paper_2507_10804_amd import psf as gpsf
+    from paper_2507_10804_amd import symbol as gsym
+
+    G = synth.symbol_grid(301, 921, 10.0, 31, r=8, rho0=0.02)
+    gc = gsym._gridc(G)
+    h = ctypes.c_void_p()
+    assert lib.fwi_symbol_create(ctypes.byref(gc), ctypes.byref(h)) == 0
+    n = ctypes.c_size_t()
+    pg = gpsf._grid(synth.psf_grid(301, 921))
+    assert lib.fwi_psfplus_workspace_size(h, ctypes.byref(pg), 16, ctypes.byref(n)) == 0
+    assert n.value > 0
+    for rank in (0, 33):
+        assert lib.fwi_psfplus_workspace_size(h, ctypes.byref(pg), rank, ctypes.byref(n)) == -1
+    other = gpsf._grid(synth.psf_grid(300, 921))  # a different model
+    assert lib.fwi_psfplus_workspace_size(h, ctypes.byref(other), 4, ctypes.byref(n)) == -1
+    wide = gpsf._grid(synth.PsfGrid(301, 921, 16, 16, 32, 32, 9, 29, 32, 2))  # W = 65 fits 360
+    assert lib.fwi_psfplus_workspace_size(h, ctypes.byref(wide), 4, ctypes.byref(n)) == 0
+    lib.fwi_symbol_destroy(h)
+    # vector algebra
+    assert lib.fwi_vec_workspace_size(0, ctypes.byref(n)) == -1
+    assert lib.fwi_vec_workspace_size(1 << 31, ctypes.byref(n)) == -1
+    assert lib.fwi_vec_workspace_size(1000, ctypes.byref(n)) == 0
+    fake = ctypes.c_void_p(256)
+    order = (ctypes.c_int * 65)(*range(65))
+    assert lib.fwi_lbfgs_loop1(1000, 65, order, fake, fake, fake, fake, fake, fake, n.value,
+                               None) == -1
+    bad = (ctypes.c_int * 1)(64)  # slot out of range
+    assert lib.fwi_lbfgs_loop2(1000, 1, bad, fake, fake, fake, fake, fake, fake, n.value,
+                               None) == -1
+    assert lib.fwi_vec_dot(1000, fake, fake, fake, fake, n.value - 8, None) == -3
