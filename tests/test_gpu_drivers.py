@@ -168,3 +168,20 @@ def test_gpcn_matches_oracle():
     e = np.linalg.norm(host(st[-1]) - st_o[-1]) / np.linalg.norm(st_o[-1])
     say(f"  final state rel-L2 {e:.2e}")
     assert e < 1e-4
+
+
+def test_dot_is_reproducible():
+    """FP64 dot products with a fixed grid and summation order: bitwise
+    identical run to run, at the full model size."""
+    import torch
+    from paper_2507_10804_amd import drivers as D
+
+    n = 301 * 921
+    say(f"case: fwi_vec_dot reproducibility, n={n}")
+    v = D.Vec(n, torch.device("cuda"))
+    rng = np.random.default_rng(5)
+    x, y = dev(torch, rng.standard_normal(n)), dev(torch, rng.standard_normal(n))
+    vals = {v.dot(x, y) for _ in range(5)}
+    assert len(vals) == 1
+    ref = float(r32(host(x)) @ r32(host(y)))
+    assert next(iter(vals)) == pytest.approx(ref, rel=1e-12)

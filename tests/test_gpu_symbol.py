@@ -296,3 +296,24 @@ def test_psf_plus_full_size():
     e = crel(host(approx(dev(torch, v))), D.psf_plus_apply(G, A, B, v))
     say(f"  apply rel-L2 {e:.2e}")
     assert e < 1e-4
+
+
+def test_apply_is_deterministic():
+    """The header promises a fixed summation order: two applies of the same
+    tables to the same vectors are bitwise identical."""
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    G = synth.SymbolGrid(64, 96, 72, 100, 5.0, 8, 0.3)
+    rng = np.random.default_rng(21)
+    T, B = 5, 3
+    A = dev(torch, rng.standard_normal((T, 64, 96)) + 1j * rng.standard_normal((T, 64, 96)),
+            torch.complex64)
+    M = dev(torch, rng.standard_normal((T, 72, 100)) + 1j * rng.standard_normal((T, 72, 100)),
+            torch.complex64)
+    v = dev(torch, rng.standard_normal((B, 64, 96)))
+    say("case: fwi_symbol_apply twice, 64x96 on 72x100, T=5, B=3")
+    sym = S.Symbol(G)
+    o1 = sym.apply(A, M, 1.0, v).cpu().numpy()
+    o2 = sym.apply(A, M, 1.0, v).cpu().numpy()
+    assert np.array_equal(o1, o2)
