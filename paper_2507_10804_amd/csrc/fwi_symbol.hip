@@ -6,7 +6,7 @@
 // FFT engine.  Complex FP32 transforms of lengths up to 2048 with factors 2,
 // 3 and 5, done in LDS: a workgroup stages whole lines -- one row, or a band
 // of adjacent columns read row by row so that global reads stay contiguous --
-// and runs self-sorting Stockham stages (radix 4, 2, 3, 5) between two LDS
+// and runs self-sorting Stockham stages (radix 8, 4, 2, 3, 5) between two LDS
 // buffers.  A 2-D transform is a row pass and a column pass.  The zero
 // padding of the FFT grid is never read (rows beyond the data are filled in
 // LDS) and the inverse passes store only model-grid rows and columns.  The
@@ -87,6 +87,30 @@ __device__ inline void dft(float2 *v) {
     v[0] = cadd(v[0], a);
     v[1] = cadd(m, ib);
     v[2] = csub(m, ib);
+  } else if constexpr (R == 8) {
+    // two radix-4 DFTs: of a_k = v_k + v_{k+4} (even outputs) and of
+    // b_k = (v_k - v_{k+4}) w^k (odd outputs), w = e^{-+ i pi / 4}
+    const float h = 0.70710678118654752f;
+    const float sg = INV ? 1.0f : -1.0f;
+    float2 a[4], b[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = cadd(v[k], v[k + 4]);
+      b[k] = csub(v[k], v[k + 4]);
+    }
+    {
+      const float2 d1 = b[1], d2 = b[2], d3 = b[3];
+      b[1] = make_float2(h * (d1.x - sg * d1.y), h * (d1.y + sg * d1.x));   // h (1 + s i) d1
+      b[2] = make_float2(-sg * d2.y, sg * d2.x);                            // s i d2
+      b[3] = make_float2(h * (-d3.x - sg * d3.y), h * (-d3.y + sg * d3.x)); // h (-1 + s i) d3
+    }
+    dft<4, INV>(a);
+    dft<4, INV>(b);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
   } else {  // R == 5
     const float c1 = 0.30901699437494742f, c2 = -0.80901699437494742f;
     const float s1 = INV ? 0.95105651629515357f : -0.95105651629515357f;
@@ -156,7 +180,8 @@ __device__ float2 *fft_lines(float2 *a, float2 *b, int pitch, int nlines, const 
   int Ns = 1;
   for (int s = 0; s < f.ns; ++s) {
     const int R = f.radix[s];
-    if (R == 4) stage<4, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    if (R == 8) stage<8, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else if (R == 4) stage<4, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else if (R == 2) stage<2, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else if (R == 3) stage<3, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else stage<5, INV>(a, b, pitch, nlines, f.n, Ns, tw);
@@ -184,8 +209,21 @@ __device__ float2 *fft_wave(float2 *a, float2 *b, const Fft1 &f, const float2 *t
     for (int j = lane; j < nR; j += 64) {
       const int k = j - qdiv(j, Ns, rNs) * Ns;
       const int base = (j - k) * R + k;
-      float2 v[5];
-      if (R == 4) {
+      float2 v[8];
+      if (R == 8) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) v[t] = a[j + t * nR];
+        if (Ns > 1)
+#pragma unroll
+          for (int t = 1; t < 8; ++t) {
+            float2 w = tw[k * t * tstep];
+            if (INV) w.y = -w.y;
+            v[t] = cmul(v[t], w);
+          }
+        dft<8, INV>(v);
+#pragma unroll
+        for (int t = 0; t < 8; ++t) b[base + t * Ns] = v[t];
+      } else if (R == 4) {
 #pragma unroll
         for (int t = 0; t < 4; ++t) v[t] = a[j + t * nR];
         if (Ns > 1)
@@ -828,7 +866,7 @@ bool factor(int n, Fft1 &f) {
   f.n = n;
   f.ns = 0;
   int m = n;
-  const int rs[4] = {4, 2, 3, 5};
+  const int rs[5] = {8, 4, 2, 3, 5};
   for (int R : rs) {
     while (m % R == 0) {
       if (f.ns == FFT_MAXST) return false;
