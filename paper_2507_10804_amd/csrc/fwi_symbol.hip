@@ -6,8 +6,9 @@
 // FFT engine.  Complex FP32 transforms of lengths up to 2048 with factors 2,
 // 3 and 5, done in LDS: a workgroup stages whole lines -- one row, or a band
 // of adjacent columns read row by row so that global reads stay contiguous --
-// and runs self-sorting Stockham stages (radix 8, 4, 2, 3, 5) between two LDS
-// buffers.  A 2-D transform is a row pass and a column pass.  The zero
+// and runs self-sorting Stockham stages (radix 8, 15, 9, 4, 2, 3, 5; 15 and 9
+// as one Cooley-Tukey step over the radix-3 and radix-5 butterflies) between
+// two LDS buffers.  A 2-D transform is a row pass and a column pass.  The zero
 // padding of the FFT grid is never read (rows beyond the data are filled in
 // LDS) and the inverse passes store only model-grid rows and columns.  The
 // pointwise products with the symbol tables happen on the loads of the
@@ -63,6 +64,39 @@ __device__ inline float2 cscale(float2 a, float s) { return make_float2(a.x * s,
 // i z (forward sign folded by the caller)
 __device__ inline float2 cmuli(float2 a) { return make_float2(-a.y, a.x); }
 
+template <int R, bool INV>
+__device__ inline void dft(float2 *v);
+
+// N = R1 * R2 point DFT by one Cooley-Tukey step: R2 DFTs of size R1 over
+// v[m + R2 k], twiddles w_N^{m k'} (cos and sin tables of 2 pi e / N), R1
+// DFTs of size R2; output index k' + R1 m'.
+template <int R1, int R2, bool INV>
+__device__ inline void dft_ct(float2 *v, const float *cw, const float *sw) {
+  constexpr int N = R1 * R2;
+  float2 w[N];
+#pragma unroll
+  for (int m = 0; m < R2; ++m) {
+    float2 t[R1];
+#pragma unroll
+    for (int k = 0; k < R1; ++k) t[k] = v[m + R2 * k];
+    dft<R1, INV>(t);
+#pragma unroll
+    for (int kp = 0; kp < R1; ++kp) {
+      const int e = (m * kp) % N;
+      w[m + R2 * kp] = e == 0 ? t[kp] : cmul(t[kp], make_float2(cw[e], INV ? sw[e] : -sw[e]));
+    }
+  }
+#pragma unroll
+  for (int kp = 0; kp < R1; ++kp) {
+    float2 t2[R2];
+#pragma unroll
+    for (int m = 0; m < R2; ++m) t2[m] = w[m + R2 * kp];
+    dft<R2, INV>(t2);
+#pragma unroll
+    for (int mp = 0; mp < R2; ++mp) v[kp + R1 * mp] = t2[mp];
+  }
+}
+
 // R-point DFT in place, sign - (forward) or + (inverse).
 template <int R, bool INV>
 __device__ inline void dft(float2 *v) {
@@ -87,6 +121,26 @@ __device__ inline void dft(float2 *v) {
     v[0] = cadd(v[0], a);
     v[1] = cadd(m, ib);
     v[2] = csub(m, ib);
+  } else if constexpr (R == 9) {
+    constexpr float c[9] = {1.0f, 0.76604444311897801f, 0.17364817766693041f,
+                            -0.49999999999999978f, -0.93969262078590832f, -0.93969262078590843f,
+                            -0.50000000000000044f, 0.17364817766692997f, 0.76604444311897779f};
+    constexpr float sn[9] = {0.0f, 0.64278760968653925f, 0.98480775301220802f,
+                             0.86602540378443871f, 0.34202014332566888f, -0.34202014332566866f,
+                             -0.86602540378443837f, -0.98480775301220813f, -0.64278760968653958f};
+    dft_ct<3, 3, INV>(v, c, sn);
+  } else if constexpr (R == 15) {
+    constexpr float c[15] = {1.0f, 0.91354545764260087f, 0.66913060635885824f,
+                             0.30901699437494745f, -0.10452846326765333f, -0.49999999999999978f,
+                             -0.80901699437494734f, -0.97814760073380569f, -0.97814760073380569f,
+                             -0.80901699437494756f, -0.50000000000000044f, -0.10452846326765423f,
+                             0.30901699437494723f, 0.66913060635885846f, 0.91354545764260098f};
+    constexpr float sn[15] = {0.0f, 0.40673664307580015f, 0.74314482547739413f,
+                              0.95105651629515353f, 0.9945218953682734f, 0.86602540378443871f,
+                              0.58778525229247325f, 0.20791169081775931f, -0.20791169081775907f,
+                              -0.58778525229247303f, -0.86602540378443837f, -0.99452189536827329f,
+                              -0.95105651629515364f, -0.74314482547739402f, -0.40673664307580015f};
+    dft_ct<3, 5, INV>(v, c, sn);
   } else if constexpr (R == 8) {
     // two radix-4 DFTs: of a_k = v_k + v_{k+4} (even outputs) and of
     // b_k = (v_k - v_{k+4}) w^k (odd outputs), w = e^{-+ i pi / 4}
@@ -174,13 +228,18 @@ __device__ inline void stage(const float2 *src, float2 *dst, int pitch, int nlin
 
 // All stages; returns the buffer that holds the result.  Every thread of the
 // workgroup must call it (it synchronises after each stage).
-template <bool INV>
+// BIG compiles the radix-15 and radix-9 stages in (their registers count
+// against every kernel that contains them): the column passes use them, the
+// row passes, whose lengths factor without them, do not.
+template <bool INV, bool BIG = false>
 __device__ float2 *fft_lines(float2 *a, float2 *b, int pitch, int nlines, const Fft1 &f,
                              const float2 *tw) {
   int Ns = 1;
   for (int s = 0; s < f.ns; ++s) {
     const int R = f.radix[s];
     if (R == 8) stage<8, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else if (BIG && R == 15) stage<15, INV>(a, b, pitch, nlines, f.n, Ns, tw);
+    else if (BIG && R == 9) stage<9, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else if (R == 4) stage<4, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else if (R == 2) stage<2, INV>(a, b, pitch, nlines, f.n, Ns, tw);
     else if (R == 3) stage<3, INV>(a, b, pitch, nlines, f.n, Ns, tw);
@@ -194,87 +253,49 @@ __device__ float2 *fft_lines(float2 *a, float2 *b, int pitch, int nlines, const 
   return a;
 }
 
-// The stages of one line run by one wavefront alone: lanes stride over the
-// butterflies, and a stage's LDS writes are ordered before the next stage's
-// reads by a wavefront fence (a wavefront issues its LDS operations in order;
-// no workgroup barrier is needed).  Returns the buffer holding the result.
+// One Stockham stage of one line run by one wavefront: lanes stride over the
+// butterflies.
+template <int R, bool INV>
+__device__ inline void wave_stage(const float2 *a, float2 *b, int n, int Ns, const float2 *tw) {
+  const int lane = threadIdx.x & 63;
+  const int nR = n / R, tstep = n / (Ns * R);
+  const float rNs = 1.0f / (float)Ns;
+  for (int j = lane; j < nR; j += 64) {
+    const int k = j - qdiv(j, Ns, rNs) * Ns;
+    float2 v[R];
+#pragma unroll
+    for (int t = 0; t < R; ++t) v[t] = a[j + t * nR];
+    if (Ns > 1) {
+#pragma unroll
+      for (int t = 1; t < R; ++t) {
+        float2 w = tw[k * t * tstep];
+        if (INV) w.y = -w.y;
+        v[t] = cmul(v[t], w);
+      }
+    }
+    dft<R, INV>(v);
+    const int base = (j - k) * R + k;
+#pragma unroll
+    for (int t = 0; t < R; ++t) b[base + t * Ns] = v[t];
+  }
+}
+
+// The stages of one line run by one wavefront alone; a stage's LDS writes
+// are ordered before the next stage's reads by a wavefront fence (a
+// wavefront issues its LDS operations in order; no workgroup barrier is
+// needed).  Returns the buffer holding the result.
 template <bool INV>
 __device__ float2 *fft_wave(float2 *a, float2 *b, const Fft1 &f, const float2 *tw) {
-  const int lane = threadIdx.x & 63;
   int Ns = 1;
   for (int s = 0; s < f.ns; ++s) {
     const int R = f.radix[s];
-    const int nR = f.n / R, tstep = f.n / (Ns * R);
-    const float rNs = 1.0f / (float)Ns;
-    for (int j = lane; j < nR; j += 64) {
-      const int k = j - qdiv(j, Ns, rNs) * Ns;
-      const int base = (j - k) * R + k;
-      float2 v[8];
-      if (R == 8) {
-#pragma unroll
-        for (int t = 0; t < 8; ++t) v[t] = a[j + t * nR];
-        if (Ns > 1)
-#pragma unroll
-          for (int t = 1; t < 8; ++t) {
-            float2 w = tw[k * t * tstep];
-            if (INV) w.y = -w.y;
-            v[t] = cmul(v[t], w);
-          }
-        dft<8, INV>(v);
-#pragma unroll
-        for (int t = 0; t < 8; ++t) b[base + t * Ns] = v[t];
-      } else if (R == 4) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = a[j + t * nR];
-        if (Ns > 1)
-#pragma unroll
-          for (int t = 1; t < 4; ++t) {
-            float2 w = tw[k * t * tstep];
-            if (INV) w.y = -w.y;
-            v[t] = cmul(v[t], w);
-          }
-        dft<4, INV>(v);
-#pragma unroll
-        for (int t = 0; t < 4; ++t) b[base + t * Ns] = v[t];
-      } else if (R == 2) {
-#pragma unroll
-        for (int t = 0; t < 2; ++t) v[t] = a[j + t * nR];
-        if (Ns > 1) {
-          float2 w = tw[k * tstep];
-          if (INV) w.y = -w.y;
-          v[1] = cmul(v[1], w);
-        }
-        dft<2, INV>(v);
-#pragma unroll
-        for (int t = 0; t < 2; ++t) b[base + t * Ns] = v[t];
-      } else if (R == 3) {
-#pragma unroll
-        for (int t = 0; t < 3; ++t) v[t] = a[j + t * nR];
-        if (Ns > 1)
-#pragma unroll
-          for (int t = 1; t < 3; ++t) {
-            float2 w = tw[k * t * tstep];
-            if (INV) w.y = -w.y;
-            v[t] = cmul(v[t], w);
-          }
-        dft<3, INV>(v);
-#pragma unroll
-        for (int t = 0; t < 3; ++t) b[base + t * Ns] = v[t];
-      } else {
-#pragma unroll
-        for (int t = 0; t < 5; ++t) v[t] = a[j + t * nR];
-        if (Ns > 1)
-#pragma unroll
-          for (int t = 1; t < 5; ++t) {
-            float2 w = tw[k * t * tstep];
-            if (INV) w.y = -w.y;
-            v[t] = cmul(v[t], w);
-          }
-        dft<5, INV>(v);
-#pragma unroll
-        for (int t = 0; t < 5; ++t) b[base + t * Ns] = v[t];
-      }
-    }
+    if (R == 8) wave_stage<8, INV>(a, b, f.n, Ns, tw);
+    else if (R == 15) wave_stage<15, INV>(a, b, f.n, Ns, tw);
+    else if (R == 9) wave_stage<9, INV>(a, b, f.n, Ns, tw);
+    else if (R == 4) wave_stage<4, INV>(a, b, f.n, Ns, tw);
+    else if (R == 2) wave_stage<2, INV>(a, b, f.n, Ns, tw);
+    else if (R == 3) wave_stage<3, INV>(a, b, f.n, Ns, tw);
+    else wave_stage<5, INV>(a, b, f.n, Ns, tw);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -325,7 +346,7 @@ __device__ const float2 *cols_fft(float2 *a, float2 *b, int pitch, int C, const 
     __syncthreads();
     return r - w * pitch;  // the same buffer for every line (same stage count)
   }
-  return fft_lines<INV>(a, b, pitch, C, f, tw);
+  return fft_lines<INV, true>(a, b, pitch, C, f, tw);
 }
 
 // Column band of a workgroup: consecutive workgroup ids go round-robin to the
@@ -862,12 +883,15 @@ T *at_(void *base, size_t off) {
 
 size_t up256(size_t b) { return (b + 255) & ~size_t(255); }
 
-bool factor(int n, Fft1 &f) {
+// Stage radices of length n, largest first; `big` admits 15 and 9 (column
+// passes only, see fft_lines).
+bool factor(int n, Fft1 &f, bool big) {
   f.n = n;
   f.ns = 0;
   int m = n;
-  const int rs[5] = {8, 4, 2, 3, 5};
-  for (int R : rs) {
+  const int all[7] = {8, 15, 9, 4, 2, 3, 5};
+  for (int R : all) {
+    if (!big && (R == 15 || R == 9)) continue;
     while (m % R == 0) {
       if (f.ns == FFT_MAXST) return false;
       f.radix[f.ns++] = R;
@@ -884,7 +908,7 @@ int check_grid(const fwi_symbol_grid *g) {
   if (g->mz < g->nz || g->mx < g->nx || g->mz > FFT_MAXN || g->mx > FFT_MAXN)
     return set_error(FWI_EINVAL, "symbol grid: need nz <= mz <= 2048 and nx <= mx <= 2048");
   Fft1 f;
-  if (!factor(g->mz, f) || !factor(g->mx, f))
+  if (!factor(g->mz, f, true) || !factor(g->mx, f, false))
     return set_error(FWI_EINVAL, "symbol grid: mz and mx must have no prime factor above 5");
   if (!(g->h > 0.0)) return set_error(FWI_EINVAL, "symbol grid: h must be positive");
   if (g->r < 2 || g->r > SYM_RMAX || (g->r & 1))
@@ -991,8 +1015,8 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   G.r = g->r;
   G.h = g->h;
   G.rho0 = g->rho0;
-  factor(g->mz, G.fz);
-  factor(g->mx, G.fx);
+  factor(g->mz, G.fz, true);
+  factor(g->mx, G.fx, false);
   for (int k = 0; k < g->r / 2; ++k) {
     const double th = 2.0 * M_PI * (k + 1) / g->r;
     G.sx[k] = g->rho0 * std::cos(th);
