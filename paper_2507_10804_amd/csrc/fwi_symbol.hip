@@ -512,6 +512,156 @@ __global__ __launch_bounds__(BNT) void k_rows_inv_blend(SymGeo g, const float2 *
   }
 }
 
+// Orders a wavefront's LDS accesses: those before complete before those
+// after (a wavefront issues its LDS operations in order; the fences stop the
+// compiler moving accesses across).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// One Stockham stage of radix R of one line of length n <= NMAX, in place,
+// run by one wavefront: every lane holds the inputs of all its butterflies
+// in registers before any lane writes.
+template <int R, bool INV, int NMAX>
+__device__ inline void wave_stage_ip(float2 *a, int n, int Ns, const float2 *tw) {
+  constexpr int IT = (NMAX / R + 63) / 64;
+  const int lane = threadIdx.x & 63;
+  const int nR = n / R, tstep = n / (Ns * R);
+  const float rNs = 1.0f / (float)Ns;
+  float2 v[IT][R];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = lane + 64 * it;
+    if (j < nR) {
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[it][t] = a[j + t * nR];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int j = lane + 64 * it;
+    if (j < nR) {
+      const int k = j - qdiv(j, Ns, rNs) * Ns;
+      if (Ns > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 w = tw[k * t * tstep];
+          if (INV) w.y = -w.y;
+          v[it][t] = cmul(v[it][t], w);
+        }
+      }
+      dft<R, INV>(v[it]);
+      const int base = (j - k) * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) a[base + t * Ns] = v[it][t];
+    }
+  }
+  wave_sync();
+}
+
+// All stages of one row line in place (result in natural order in `a`).
+// Row lengths are factored without the radix-15 and radix-9 stages, whose
+// register arrays would bound the occupancy of every kernel holding them.
+template <bool INV, int NMAX>
+__device__ void fft_wave_ip(float2 *a, const Fft1 &f, const float2 *tw) {
+  int Ns = 1;
+  for (int s = 0; s < f.ns; ++s) {
+    const int R = f.radix[s];
+    if (R == 8) wave_stage_ip<8, INV, NMAX>(a, f.n, Ns, tw);
+    else if (R == 4) wave_stage_ip<4, INV, NMAX>(a, f.n, Ns, tw);
+    else if (R == 2) wave_stage_ip<2, INV, NMAX>(a, f.n, Ns, tw);
+    else if (R == 3) wave_stage_ip<3, INV, NMAX>(a, f.n, Ns, tw);
+    else wave_stage_ip<5, INV, NMAX>(a, f.n, Ns, tw);
+    Ns *= R;
+  }
+}
+
+// The blend with wavefronts owning lines: the W wavefronts of workgroup
+// (row, j) form W / S groups of S, group q taking vector j * W / S + q and
+// its wavefront p the terms t = p, p + S, ...; each term is an inverse row
+// transform in the wavefront's own LDS line (no workgroup barrier between
+// stages or terms), Re(A_t z_t) accumulated for the lane's columns
+// x = lane + 64 i in registers.  With S > 1 the group's partial sums are
+// added through LDS in wavefront order (S > 1 keeps every CU busy when B is
+// small).  NMAX >= mx bounds the per-lane arrays.
+template <int NMAX>
+__global__ __launch_bounds__(256) void k_rows_inv_blend_w(SymGeo g, const float2 *__restrict__ z,
+                                                         int T, int B, int S,
+                                                         const float2 *__restrict__ A,
+                                                         float scale, float *__restrict__ out) {
+  constexpr int NACC = NMAX / 64;
+  extern __shared__ float2 sm[];
+  const int n = g.mx, nz = g.nz, nx = g.nx;
+  const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2 *tw = sm, *a = sm + n + w * n;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = g.fx.tw[i];
+  __syncthreads();
+  const int q = w / S, p = w - q * S;
+  const int row = blockIdx.x, v = blockIdx.y * (W / S) + q;
+  const bool live = v < B;  // uniform over the wavefront
+  float acc[NACC];
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) acc[i] = 0.0f;
+  for (int t = p; live && t < T; t += S) {
+    const float2 *zr = z + (((long long)v * T + t) * nz + row) * n;
+    for (int base = lane; base < n; base += 8 * 64) {
+      float2 tmp[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + 64 * u;
+        tmp[u] = i < n ? zr[i] : make_float2(0.0f, 0.0f);
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int i = base + 64 * u;
+        if (i < n) a[i] = tmp[u];
+      }
+    }
+    wave_sync();
+    fft_wave_ip<true, NMAX>(a, g.fx, tw);
+    const float2 *Ar = A + ((long long)t * nz + row) * nx;
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) {
+      const int x = lane + 64 * i;
+      if (x < nx) {
+        const float2 c = Ar[x], y = a[x];
+        acc[i] = fmaf(c.x, y.x, fmaf(-c.y, y.y, acc[i]));
+      }
+    }
+    wave_sync();  // the next term's loads overwrite the line
+  }
+  if (S > 1) {  // uniform over the workgroup
+    float *part = reinterpret_cast<float *>(a);  // 2 n floats >= nx
+#pragma unroll
+    for (int i = 0; i < NACC; ++i) {
+      const int x = lane + 64 * i;
+      if (x < nx) part[x] = acc[i];
+    }
+    __syncthreads();
+    if (p == 0) {
+      for (int k = 1; k < S; ++k) {
+        const float *pk = reinterpret_cast<const float *>(a + k * n);
+#pragma unroll
+        for (int i = 0; i < NACC; ++i) {
+          const int x = lane + 64 * i;
+          if (x < nx) acc[i] += pk[x];
+        }
+      }
+    }
+  }
+  if (!live || p != 0) return;
+  const float f = scale / ((float)g.mz * (float)g.mx);
+  float *o = out + ((long long)v * nz + row) * nx;
+#pragma unroll
+  for (int i = 0; i < NACC; ++i) {
+    const int x = lane + 64 * i;
+    if (x < nx) o[x] = acc[i] * f;
+  }
+}
+
 // Inverse row transforms of z[0][t][row] and demodulation by the sample
 // frequency: cols[t][row][x] = z_t e^{-i x.xi_t} / M (phase in FP64).  Grid
 // (nz, T).
@@ -865,6 +1015,8 @@ struct fwi_symbol {
   size_t zchunk = (size_t)4 << 30;  // bytes of partial transforms per vector chunk
   int bg = 4;                 // vectors per blend workgroup
   int tc = 0;                 // terms per blend step (0: as many as LDS allows, at most 4)
+  int blend = 1;              // 1: wavefronts own lines; 0: workgroup-shared lines
+  int split = 0;              // wavefronts per vector of the blend (0: by grid size)
 };
 
 namespace {
@@ -942,6 +1094,37 @@ int blend_terms(int nx, int mx, int T) {
 }
 size_t blend_lds(int nx, int mx, int TC) { return sizeof(float2) * (size_t)TC * (nx + 2 * (size_t)mx); }
 
+// Wavefronts per workgroup of the one-wavefront-per-vector blend: a line of
+// mx values each plus the twiddles within the LDS budget (3 or 4 for mx <=
+// 2048).
+int blend_waves(int mx) { return std::min(4, (int)(LDS_BUDGET / sizeof(float2) - mx) / mx); }
+
+// Wavefronts per vector of the blend: split the terms while the grid holds
+// fewer than `target` wavefronts (S divides W, S <= T).
+int blend_split(int W, int nz, int nb, int T, int target) {
+  int S = 1;
+  for (int c = 2; c <= W; ++c)
+    if (W % c == 0 && c <= T && (long long)nz * nb * S < target) S = c;
+  return S;
+}
+
+int blend_w(const fwi_symbol *s, const SymGeo &g, const float2 *z, int T, int nb,
+            const float2 *A, float scale, float *out, hipStream_t st) {
+  const int W = blend_waves(g.mx);
+  const int S = s->split ? (W % s->split == 0 ? std::min(s->split, W) : 1)
+                         : blend_split(W, g.nz, nb, T, 8192);
+  const int vpw = W / S;
+  const dim3 grid(g.nz, (nb + vpw - 1) / vpw), block(64 * W);
+  const size_t lds = sizeof(float2) * (size_t)g.mx * (1 + W);
+  if (g.mx <= 512)
+    hipLaunchKernelGGL(k_rows_inv_blend_w<512>, grid, block, lds, st, g, z, T, nb, S, A, scale, out);
+  else if (g.mx <= 1024)
+    hipLaunchKernelGGL(k_rows_inv_blend_w<1024>, grid, block, lds, st, g, z, T, nb, S, A, scale, out);
+  else
+    hipLaunchKernelGGL(k_rows_inv_blend_w<2048>, grid, block, lds, st, g, z, T, nb, S, A, scale, out);
+  return FWI_OK;
+}
+
 // Vectors per chunk of an apply: the partial transforms of one chunk stay
 // within `zchunk` bytes (default 4 GiB: measured, smaller chunks that keep
 // them in the last-level cache lose more to lower parallelism than they gain).
@@ -1007,6 +1190,8 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
   if (const char *e = std::getenv("FWI_SYM_BG")) s->bg = std::max(1, std::min(BGMAX, std::atoi(e)));
   if (const char *e = std::getenv("FWI_SYM_TC")) s->tc = std::max(0, std::min(4, std::atoi(e)));
+  if (const char *e = std::getenv("FWI_SYM_BLEND")) s->blend = std::atoi(e) != 0;
+  if (const char *e = std::getenv("FWI_SYM_SPLIT")) s->split = std::max(0, std::min(4, std::atoi(e)));
   SymGeo &G = s->g;
   G.nz = g->nz;
   G.nx = g->nx;
@@ -1083,9 +1268,15 @@ int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float
     const int nb = std::min(Bc, B - b0);
     if (int rc = forward(s, v + b0 * plane, g.nz, g.nx, nb, rowt, spec, st)) return rc;
     if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, nb, z, st)) return rc;
-    hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(BNT),
-                       blend_lds(g.nx, g.mx, TC), st, g, z, T, TC, nb, s->bg,
-                       reinterpret_cast<const float2 *>(A), scale, out + b0 * plane);
+    if (s->blend) {
+      if (int rc = blend_w(s, g, z, T, nb, reinterpret_cast<const float2 *>(A), scale,
+                           out + b0 * plane, st))
+        return rc;
+    } else {
+      hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(BNT),
+                         blend_lds(g.nx, g.mx, TC), st, g, z, T, TC, nb, s->bg,
+                         reinterpret_cast<const float2 *>(A), scale, out + b0 * plane);
+    }
     SY_TRY(hipGetLastError());
   }
   return FWI_OK;
