@@ -8,7 +8,9 @@
 // of adjacent columns read row by row so that global reads stay contiguous --
 // and runs self-sorting Stockham stages (radix 8, 15, 9, 4, 2, 3, 5; 15 and 9
 // as one Cooley-Tukey step over the radix-3 and radix-5 butterflies) between
-// two LDS buffers.  A 2-D transform is a row pass and a column pass.  The zero
+// two LDS buffers, or -- in the blend -- in place in one line per wavefront,
+// with no workgroup barrier between stages.  A 2-D transform is a row pass
+// and a column pass.  The zero
 // padding of the FFT grid is never read (rows beyond the data are filled in
 // LDS) and the inverse passes store only model-grid rows and columns.  The
 // pointwise products with the symbol tables happen on the loads of the
@@ -36,7 +38,6 @@ constexpr int SYM_RMAX = 16;   // PDO directions
 constexpr int PP_RANK = 32;    // PSF+ rank
 constexpr int NTH = 256;
 constexpr int CNT = 512;  // threads of the column passes (8 waves per band)
-constexpr int BNT = 512;  // threads of the blend pass
 constexpr int LDS_BUDGET = 65536;
 constexpr double TIE = 1e-9;   // relative distance tolerance of the separation
 
@@ -437,77 +438,6 @@ __global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__rest
     if (col0 + c < mx) {
       const float2 r = res[c * pitch + i];
       __builtin_nontemporal_store(f2v{r.x, r.y}, Z + (long long)i * mx + col0 + c);
-    }
-  }
-}
-
-constexpr int ACC = FFT_MAXN / BNT;  // model columns per thread of the blend
-
-// Inverse row transforms of z[b][t][row] for all t and the blend
-// out[b][row][x] = scale / M sum_t Re(A_t(row, x) z_t(row, x)), x < nx.
-// Grid (nz, ceil(B / BG)): a workgroup owns one row of BG vectors, so each
-// coefficient row A_t(row, :) is staged in LDS once for all of them; TC terms
-// are transformed at a time.
-constexpr int BGMAX = 4;
-
-__global__ __launch_bounds__(BNT) void k_rows_inv_blend(SymGeo g, const float2 *__restrict__ z,
-                                                        int T, int TC, int B, int BG,
-                                                        const float2 *__restrict__ A, float scale,
-                                                        float *__restrict__ out) {
-  extern __shared__ float2 sm[];
-  const int n = g.mx, nz = g.nz, nx = g.nx;
-  float2 *As = sm, *a = sm + TC * nx, *b = a + TC * n;
-  const float2 *tw = g.fx.tw;
-  const int row = blockIdx.x;
-  const int b0 = blockIdx.y * BG;
-  const int nb = min(BG, B - b0);
-  float acc[BGMAX][ACC];
-#pragma unroll
-  for (int v = 0; v < BGMAX; ++v)
-#pragma unroll
-    for (int i = 0; i < ACC; ++i) acc[v][i] = 0.0f;
-  for (int t0 = 0; t0 < T; t0 += TC) {
-    const int nl = min(TC, T - t0);
-    for (int l = 0; l < nl; ++l) {
-      const float2 *Ar = A + ((long long)(t0 + l) * nz + row) * nx;
-      staged<4, BNT>(nx, [&](int x) { return Ar[x]; }, [&](int x, float2 v) { As[l * nx + x] = v; });
-    }
-#pragma unroll
-    for (int v = 0; v < BGMAX; ++v) {
-      if (v < nb) {  // uniform over the workgroup
-        for (int l = 0; l < nl; ++l) {
-          const float2 *zr = z + (((long long)(b0 + v) * T + t0 + l) * nz + row) * n;
-          staged<4, BNT>(n, [&](int i) { return zr[i]; }, [&](int i, float2 w) { a[l * n + i] = w; });
-        }
-        __syncthreads();
-        const float2 *res = fft_lines<true>(a, b, n, nl, g.fx, tw);
-#pragma unroll
-        for (int i = 0; i < ACC; ++i) {
-          const int x = threadIdx.x + i * BNT;
-          if (x < nx) {
-            float s = acc[v][i];
-            for (int l = 0; l < nl; ++l) {
-              const float2 c = As[l * nx + x];
-              const float2 y = res[l * n + x];
-              s = fmaf(c.x, y.x, fmaf(-c.y, y.y, s));
-            }
-            acc[v][i] = s;
-          }
-        }
-        __syncthreads();
-      }
-    }
-  }
-  const float f = scale / ((float)g.mz * (float)g.mx);
-#pragma unroll
-  for (int v = 0; v < BGMAX; ++v) {
-    if (v < nb) {
-      float *o = out + ((long long)(b0 + v) * nz + row) * nx;
-#pragma unroll
-      for (int i = 0; i < ACC; ++i) {
-        const int x = threadIdx.x + i * BNT;
-        if (x < nx) o[x] = acc[v][i] * f;
-      }
     }
   }
 }
@@ -1013,9 +943,6 @@ struct fwi_symbol {
   size_t off_tz = 0;         // float2 offset of the mz table
   void *dev = nullptr;
   size_t zchunk = (size_t)4 << 30;  // bytes of partial transforms per vector chunk
-  int bg = 4;                 // vectors per blend workgroup
-  int tc = 0;                 // terms per blend step (0: as many as LDS allows, at most 4)
-  int blend = 1;              // 1: wavefronts own lines; 0: workgroup-shared lines
   int split = 0;              // wavefronts per vector of the blend (0: by grid size)
 };
 
@@ -1088,13 +1015,8 @@ int col_band(int mz) {  // log2 of the band width
 unsigned band_grid(int mx, int C) { return (unsigned)(8 * (((mx + C - 1) / C + 7) / 8)); }
 size_t col_lds(int mz, int cs) { return sizeof(float2) * (mz + 2 * ((size_t)1 << cs) * (mz + 1)); }
 size_t row_lds(int mx) { return sizeof(float2) * 2 * (size_t)mx; }
-// Terms per blend step: LDS holds TC coefficient rows and two TC-line buffers.
-int blend_terms(int nx, int mx, int T) {
-  return std::max(1, std::min({4, T, (LDS_BUDGET / (int)sizeof(float2)) / (nx + 2 * mx)}));
-}
-size_t blend_lds(int nx, int mx, int TC) { return sizeof(float2) * (size_t)TC * (nx + 2 * (size_t)mx); }
 
-// Wavefronts per workgroup of the one-wavefront-per-vector blend: a line of
+// Wavefronts per workgroup of the blend: a line of
 // mx values each plus the twiddles within the LDS budget (3 or 4 for mx <=
 // 2048).
 int blend_waves(int mx) { return std::min(4, (int)(LDS_BUDGET / sizeof(float2) - mx) / mx); }
@@ -1188,9 +1110,6 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   fwi_symbol *s = new fwi_symbol;
   s->gi = *g;
   if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
-  if (const char *e = std::getenv("FWI_SYM_BG")) s->bg = std::max(1, std::min(BGMAX, std::atoi(e)));
-  if (const char *e = std::getenv("FWI_SYM_TC")) s->tc = std::max(0, std::min(4, std::atoi(e)));
-  if (const char *e = std::getenv("FWI_SYM_BLEND")) s->blend = std::atoi(e) != 0;
   if (const char *e = std::getenv("FWI_SYM_SPLIT")) s->split = std::max(0, std::min(4, std::atoi(e)));
   SymGeo &G = s->g;
   G.nz = g->nz;
@@ -1262,21 +1181,14 @@ int fwi_symbol_apply(fwi_symbol *s, int T, const float *A, const float *M, float
   const SymGeo &g = s->g;
   float2 *spec = at_<float2>(ws, L.spec), *rowt = at_<float2>(ws, L.rowt), *z = at_<float2>(ws, L.z);
   const int Bc = apply_chunk(s, B, T);
-  const int TC = s->tc ? std::min(s->tc, blend_terms(g.nx, g.mx, T)) : blend_terms(g.nx, g.mx, T);
   const long long plane = (long long)g.nz * g.nx;
   for (int b0 = 0; b0 < B; b0 += Bc) {
     const int nb = std::min(Bc, B - b0);
     if (int rc = forward(s, v + b0 * plane, g.nz, g.nx, nb, rowt, spec, st)) return rc;
     if (int rc = inverse_cols(s, spec, reinterpret_cast<const float2 *>(M), T, nb, z, st)) return rc;
-    if (s->blend) {
-      if (int rc = blend_w(s, g, z, T, nb, reinterpret_cast<const float2 *>(A), scale,
-                           out + b0 * plane, st))
-        return rc;
-    } else {
-      hipLaunchKernelGGL(k_rows_inv_blend, dim3(g.nz, (nb + s->bg - 1) / s->bg), dim3(BNT),
-                         blend_lds(g.nx, g.mx, TC), st, g, z, T, TC, nb, s->bg,
-                         reinterpret_cast<const float2 *>(A), scale, out + b0 * plane);
-    }
+    if (int rc = blend_w(s, g, z, T, nb, reinterpret_cast<const float2 *>(A), scale,
+                         out + b0 * plane, st))
+      return rc;
     SY_TRY(hipGetLastError());
   }
   return FWI_OK;

@@ -85,6 +85,34 @@ def test_apply_matches_oracle(shape):
         assert e < 1e-5
 
 
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_apply_blend_splits(split):
+    """The blend with 1, 2 or 4 wavefronts sharing one vector's terms (the
+    size rule picks 1 only for large batches): each against the oracle, on a
+    batch that leaves wavefronts idle in the last workgroup."""
+    import os
+
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    G = synth.SymbolGrid(30, 50, 32, 54, 1.0, 8, 0.5)
+    rng = np.random.default_rng(13)
+    T, B = 7, 3
+    A = r32(rng.standard_normal((T, 30, 50)) + 1j * rng.standard_normal((T, 30, 50)))
+    M = r32(rng.standard_normal((T, 32, 54)) + 1j * rng.standard_normal((T, 32, 54)))
+    v = r32(rng.standard_normal((B, 30, 50)))
+    say(f"case: fwi_symbol_apply 30x50 on 32x54, T={T}, B={B}, FWI_SYM_SPLIT={split}")
+    os.environ["FWI_SYM_SPLIT"] = str(split)
+    try:
+        sym = S.Symbol(G)
+    finally:
+        del os.environ["FWI_SYM_SPLIT"]
+    got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 0.5,
+                         dev(torch, v)))
+    for b in range(B):
+        assert crel(got[b], 0.5 * D.symbol_apply(G, A, M, v[b])) < 1e-5
+
+
 def test_apply_many_terms_and_vectors():
     """T above one LDS batch of terms, B > 1: every (vector, term) pair."""
     import torch
