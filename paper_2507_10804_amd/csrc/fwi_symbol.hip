@@ -592,6 +592,141 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_w(SymGeo g, const float2
   }
 }
 
+// The blend for rows of 960 = 15 x 64 points (the FFT grid of the 921 x 301
+// model), with the line split so that most of the transform stays in
+// registers.  With k = 64 k1 + k2 and n = n1 + 15 n2 the inverse DFT is
+//   y[n1 + 15 n2] = sum_k2 w64^(n2 k2) w960^(n1 k2) sum_k1 x[64 k1 + k2] w15^(n1 k1)
+// (w_L = e^(2 pi i / L)): lane k2 loads its 15 values straight from global
+// memory (coalesced) and does the radix-15 DFT in registers; the 15 64-point
+// DFTs over k2 = 8 a + b, n2 = c + 8 d are two radix-8 passes through LDS,
+//   Z[c][b] = w64^(c b) sum_a V[8 a + b] w8^(c a),  y = sum_b w8^(d b) Z[c][b],
+// lanes taking (n1, b) and then (n1, c) pairs.  Rows of the LDS line are
+// BL_P = 72 slots apart and Z[c][b] sits at 8 c + (b ^ c), which keeps every
+// 16-lane group of every pass on distinct banks.  Three LDS passes per line
+// instead of the Stockham form's five; the same workgroup and term-split
+// structure as k_rows_inv_blend_w.  Lane (n1, c) ends with the outputs
+// x = n1 + 15 (c + 8 d).
+constexpr int BL_P = 72;
+
+__global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const float2 *__restrict__ z,
+                                                           int T, int B, int S,
+                                                           const float2 *__restrict__ A,
+                                                           float scale, float *__restrict__ out) {
+  extern __shared__ float2 sm[];
+  constexpr int N = 960, LINE = 15 * BL_P;
+  const int nz = g.nz, nx = g.nx;
+  const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2 *T2 = sm;        // [n1][k2]: w960^(n1 k2)
+  float2 *T3 = sm + N;    // [c][b]: w64^(c b)
+  float2 *a = sm + N + 64 + w * LINE;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    float2 t = g.fx.tw[((i >> 6) * (i & 63)) % N];
+    T2[i] = make_float2(t.x, -t.y);
+  }
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    float2 t = g.fx.tw[15 * (i >> 3) * (i & 7)];
+    T3[i] = make_float2(t.x, -t.y);
+  }
+  __syncthreads();
+  const int q = w / S, p = w - q * S;
+  const int row = blockIdx.x, v = blockIdx.y * (W / S) + q;
+  const bool live = v < B;  // uniform over the wavefront
+  float acc[2][8];
+#pragma unroll
+  for (int it = 0; it < 2; ++it)
+#pragma unroll
+    for (int d = 0; d < 8; ++d) acc[it][d] = 0.0f;
+  for (int t = p; live && t < T; t += S) {
+    const float2 *zr = z + (((long long)v * T + t) * nz + row) * N;
+    float2 u[15];
+#pragma unroll
+    for (int k1 = 0; k1 < 15; ++k1) u[k1] = zr[64 * k1 + lane];
+    dft<15, true>(u);
+#pragma unroll
+    for (int n1 = 0; n1 < 15; ++n1) a[n1 * BL_P + lane] = n1 ? cmul(u[n1], T2[n1 * 64 + lane]) : u[0];
+    wave_sync();
+    float2 v8[2][8];
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int pp = lane + 64 * it, n1 = pp >> 3, b = pp & 7;
+      if (pp < 120) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v8[it][k] = a[n1 * BL_P + 8 * k + b];
+      }
+    }
+    wave_sync();
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int pp = lane + 64 * it, n1 = pp >> 3, b = pp & 7;
+      if (pp < 120) {
+        dft<8, true>(v8[it]);
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          a[n1 * BL_P + 8 * c + (b ^ c)] = c ? cmul(v8[it][c], T3[c * 8 + b]) : v8[it][0];
+      }
+    }
+    wave_sync();
+    const float2 *Ar = A + ((long long)t * nz + row) * nx;
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
+      if (pp < 120) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) v8[it][k] = a[n1 * BL_P + 8 * c + (k ^ c)];
+        dft<8, true>(v8[it]);
+#pragma unroll
+        for (int d = 0; d < 8; ++d) {
+          const int x = n1 + 15 * (c + 8 * d);
+          if (x < nx) {
+            const float2 cf = Ar[x], y = v8[it][d];
+            acc[it][d] = fmaf(cf.x, y.x, fmaf(-cf.y, y.y, acc[it][d]));
+          }
+        }
+      }
+    }
+    wave_sync();  // the next term's writes come after these reads
+  }
+  if (S > 1) {  // uniform over the workgroup
+    float *part = reinterpret_cast<float *>(a);  // 2 LINE floats >= nx
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+      const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
+#pragma unroll
+      for (int d = 0; d < 8; ++d) {
+        const int x = n1 + 15 * (c + 8 * d);
+        if (pp < 120 && x < nx) part[x] = acc[it][d];
+      }
+    }
+    __syncthreads();
+    if (p == 0) {
+      for (int k = 1; k < S; ++k) {
+        const float *pk = reinterpret_cast<const float *>(a + k * LINE);
+#pragma unroll
+        for (int it = 0; it < 2; ++it) {
+          const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
+#pragma unroll
+          for (int d = 0; d < 8; ++d) {
+            const int x = n1 + 15 * (c + 8 * d);
+            if (pp < 120 && x < nx) acc[it][d] += pk[x];
+          }
+        }
+      }
+    }
+  }
+  if (!live || p != 0) return;
+  const float f = scale / ((float)g.mz * (float)N);
+  float *o = out + ((long long)v * nz + row) * nx;
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+      const int x = n1 + 15 * (c + 8 * d);
+      if (pp < 120 && x < nx) o[x] = acc[it][d] * f;
+    }
+  }
+}
+
 // Inverse row transforms of z[0][t][row] and demodulation by the sample
 // frequency: cols[t][row][x] = z_t e^{-i x.xi_t} / M (phase in FP64).  Grid
 // (nz, T).
@@ -944,6 +1079,7 @@ struct fwi_symbol {
   void *dev = nullptr;
   size_t zchunk = (size_t)4 << 30;  // bytes of partial transforms per vector chunk
   int split = 0;              // wavefronts per vector of the blend (0: by grid size)
+  int r960 = 1;               // 1: the 15 x 64 blend for 960-point rows
 };
 
 namespace {
@@ -1038,7 +1174,10 @@ int blend_w(const fwi_symbol *s, const SymGeo &g, const float2 *z, int T, int nb
   const int vpw = W / S;
   const dim3 grid(g.nz, (nb + vpw - 1) / vpw), block(64 * W);
   const size_t lds = sizeof(float2) * (size_t)g.mx * (1 + W);
-  if (g.mx <= 512)
+  if (g.mx == 960 && s->r960) {
+    const size_t l960 = sizeof(float2) * (960 + 64 + (size_t)W * 15 * BL_P);
+    hipLaunchKernelGGL(k_rows_inv_blend_960, grid, block, l960, st, g, z, T, nb, S, A, scale, out);
+  } else if (g.mx <= 512)
     hipLaunchKernelGGL(k_rows_inv_blend_w<512>, grid, block, lds, st, g, z, T, nb, S, A, scale, out);
   else if (g.mx <= 1024)
     hipLaunchKernelGGL(k_rows_inv_blend_w<1024>, grid, block, lds, st, g, z, T, nb, S, A, scale, out);
@@ -1111,6 +1250,7 @@ int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   s->gi = *g;
   if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
   if (const char *e = std::getenv("FWI_SYM_SPLIT")) s->split = std::max(0, std::min(4, std::atoi(e)));
+  if (const char *e = std::getenv("FWI_SYM_R960")) s->r960 = std::atoi(e) != 0;
   SymGeo &G = s->g;
   G.nz = g->nz;
   G.nx = g->nx;

@@ -113,6 +113,36 @@ def test_apply_blend_splits(split):
         assert crel(got[b], 0.5 * D.symbol_apply(G, A, M, v[b])) < 1e-5
 
 
+@pytest.mark.parametrize("split", [1, 2, 4])
+def test_apply_960_point_rows(split):
+    """Rows of 960 points take the 15 x 64 split transform: against the oracle
+    with 1, 2 and 4 wavefronts per vector, T odd, B leaving wavefronts idle,
+    and model rows ending inside the last radix-8 group (nx = 921)."""
+    import os
+
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    G = synth.SymbolGrid(6, 921, 8, 960, 10.0, 8, 0.02)
+    rng = np.random.default_rng(17)
+    T, B = 5, 3
+    A = r32(rng.standard_normal((T, 6, 921)) + 1j * rng.standard_normal((T, 6, 921)))
+    M = r32(rng.standard_normal((T, 8, 960)) + 1j * rng.standard_normal((T, 8, 960)))
+    v = r32(rng.standard_normal((B, 6, 921)))
+    say(f"case: fwi_symbol_apply 6x921 on 8x960, T={T}, B={B}, FWI_SYM_SPLIT={split}")
+    os.environ["FWI_SYM_SPLIT"] = str(split)
+    try:
+        sym = S.Symbol(G)
+    finally:
+        del os.environ["FWI_SYM_SPLIT"]
+    got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 2.0,
+                         dev(torch, v)))
+    for b in range(B):
+        e = crel(got[b], 2.0 * D.symbol_apply(G, A, M, v[b]))
+        say(f"  vector {b}: rel-L2 {e:.2e}")
+        assert e < 1e-5
+
+
 def test_apply_many_terms_and_vectors():
     """T above one LDS batch of terms, B > 1: every (vector, term) pair."""
     import torch
