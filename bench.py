@@ -788,7 +788,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
-              "with one all-reduce of the images, which this build does not run; "
+              "with one all-reduce of the images, which is not implemented here; "
               "use --gpus 1", file=sys.stderr)
         sys.exit(2)
 

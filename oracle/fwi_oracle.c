@@ -19,8 +19,9 @@
  *             grad = inv_noise_var sum_s J_s^T (d_s - dobs_s)
  *   gn_hvp    H v = inv_noise_var sum_s J_s^T J_s v
  *
- * The paper leaves the discretisation open (Section 4.2 only says "finite
- * differences"); the scheme below is the reading this build fixes:
+ * The paper leaves the discretisation open (Section 4.2 names finite
+ * differences and fixes no scheme); the scheme below is the reading adopted
+ * here:
  *   - padded grid NZp x NXp = (nz+2nb) x (nx+2nb), zero outside it;
  *   - L = 8th-order centred second differences in x and z (spacing dx);
  *   - sponge kappa = kappa_max((dx_pad/nb)^2 + (dz_pad/nb)^2), where dx_pad,
