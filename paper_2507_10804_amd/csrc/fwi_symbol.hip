@@ -6,7 +6,7 @@
 // FFT engine.  Complex FP32 transforms of lengths up to 2048 with factors 2,
 // 3 and 5, done in LDS: a workgroup stages whole lines -- one row, or a band
 // of adjacent columns read row by row so that global reads stay contiguous --
-// and runs self-sorting Stockham stages (radix 8, 15, 9, 4, 2, 3, 5; 15 and 9
+// and runs self-sorting Stockham stages (radix 8, 9, 15, 4, 2, 3, 5; 9 and 15
 // as one Cooley-Tukey step over the radix-3 and radix-5 butterflies) between
 // two LDS buffers, or -- in the blend -- in place in one line per wavefront,
 // with no workgroup barrier between stages.  A 2-D transform is a row pass
@@ -1104,7 +1104,7 @@ bool factor(int n, Fft1 &f, bool big) {
   f.n = n;
   f.ns = 0;
   int m = n;
-  const int all[7] = {8, 15, 9, 4, 2, 3, 5};
+  const int all[7] = {8, 9, 15, 4, 2, 3, 5};
   for (int R : all) {
     if (!big && (R == 15 || R == 9)) continue;
     while (m % R == 0) {
