@@ -184,6 +184,24 @@ __device__ inline void dft(float2 *v) {
   }
 }
 
+// float2 loads and stores at a byte offset from a workgroup-uniform base, as
+// raw buffer accesses: the base lives in a scalar descriptor and each access
+// needs one 32-bit offset (a pointer costs a 64-bit address computation per
+// access, and the column passes issue VALU work at the SIMDs' capacity).
+// Offsets stay below 2^31: at most 2048 x 2048 values of 8 bytes per plane.
+// Descriptor word 3 is the gfx9-family raw-buffer format.
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+__device__ inline __amdgpu_buffer_rsrc_t brsrc(const void *base) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, 0x7fffffff, 0x00020000);
+}
+__device__ inline float2 bld2(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <int POLICY = 0>  // 2: non-temporal
+__device__ inline void bst2(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, POLICY);
+}
+
 // a / b for 0 <= a < 2^20 and 1 <= b <= 2^16, rb = 1/b in FP32: the estimate
 // is off by at most one and is corrected exactly (a runtime integer division
 // costs dozens of instructions, this five).
@@ -389,10 +407,11 @@ __global__ __launch_bounds__(CNT) void k_cols_fwd(SymGeo g, const float2 *__rest
   load_tw(tw, g.fz);
   const int col0 = band * C;
   const long long bz = blockIdx.y;
+  const __amdgpu_buffer_rsrc_t rin = brsrc(in + bz * rows_in * mx), rout = brsrc(out + bz * n * mx);
   staged<8, CNT>(n * C,
             [&](int e) {
               const int i = e >> cs, c = e & (C - 1);
-              return (i < rows_in && col0 + c < mx) ? in[(bz * rows_in + i) * mx + col0 + c]
+              return (i < rows_in && col0 + c < mx) ? bld2(rin, (i * mx + col0 + c) << 3)
                                                     : make_float2(0.0f, 0.0f);
             },
             [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
@@ -400,7 +419,7 @@ __global__ __launch_bounds__(CNT) void k_cols_fwd(SymGeo g, const float2 *__rest
   const float2 *res = cols_fft<false>(a, b, pitch, C, g.fz, tw);
   for (int e = threadIdx.x; e < n * C; e += CNT) {
     const int i = e >> cs, c = e & (C - 1);
-    if (col0 + c < mx) out[(bz * n + i) * mx + col0 + c] = res[c * pitch + i];
+    if (col0 + c < mx) bst2(rout, (i * mx + col0 + c) << 3, res[c * pitch + i]);
   }
 }
 
@@ -417,14 +436,13 @@ __global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__rest
   load_tw(tw, g.fz);
   const int col0 = band * C;
   const long long t = blockIdx.y, bv = blockIdx.z;
-  const float2 *S = spec + bv * n * mx;
-  const float2 *W = Mt + t * n * mx;
+  const __amdgpu_buffer_rsrc_t rS = brsrc(spec + bv * n * mx), rW = brsrc(Mt + t * n * mx);
   staged<4, CNT>(n * C,
             [&](int e) {
               const int i = e >> cs, c = e & (C - 1);
               if (col0 + c >= mx) return make_float2(0.0f, 0.0f);
-              const long long o = (long long)i * mx + col0 + c;
-              return cmul(S[o], W[o]);
+              const int o = (i * mx + col0 + c) << 3;
+              return cmul(bld2(rS, o), bld2(rW, o));
             },
             [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
   __syncthreads();
@@ -432,13 +450,10 @@ __global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__rest
   // streaming stores: the partial transforms are read once, by the next pass;
   // allocating them in L2 would evict the table and spectrum bands that the
   // other vectors' and terms' workgroups re-read
-  f2v *Z = reinterpret_cast<f2v *>(z + (bv * T + t) * (long long)g.nz * mx);
+  const __amdgpu_buffer_rsrc_t rZ = brsrc(z + (bv * T + t) * (long long)g.nz * mx);
   for (int e = threadIdx.x; e < g.nz * C; e += CNT) {
     const int i = e >> cs, c = e & (C - 1);
-    if (col0 + c < mx) {
-      const float2 r = res[c * pitch + i];
-      __builtin_nontemporal_store(f2v{r.x, r.y}, Z + (long long)i * mx + col0 + c);
-    }
+    if (col0 + c < mx) bst2<2>(rZ, (i * mx + col0 + c) << 3, res[c * pitch + i]);
   }
 }
 
