@@ -326,6 +326,58 @@ __device__ float2 *fft_wave(float2 *a, float2 *b, const Fft1 &f, const float2 *t
   return a;
 }
 
+// One Stockham stage with compile-time sizes (line length N, radix R,
+// sub-transform length NS), run by one wavefront: the read and write offsets
+// t nR and t NS become immediate LDS offsets and j mod NS a multiply by a
+// constant, which matters because the column passes issue VALU work at the
+// SIMDs' capacity.  Same arithmetic, in the same order, as wave_stage.
+template <int R, bool INV, int N, int NS>
+__device__ inline void wave_stage_c(const float2 *a, float2 *b, const float2 *tw) {
+  constexpr int nR = N / R, tstep = N / (NS * R);
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int it = 0; it < (nR + 63) / 64; ++it) {
+    const int j = lane + 64 * it;
+    if (j < nR) {
+      const int k = j % NS;
+      float2 v[R];
+#pragma unroll
+      for (int t = 0; t < R; ++t) v[t] = a[j + t * nR];
+      if (NS > 1) {
+#pragma unroll
+        for (int t = 1; t < R; ++t) {
+          float2 w = tw[k * t * tstep];
+          if (INV) w.y = -w.y;
+          v[t] = cmul(v[t], w);
+        }
+      }
+      dft<R, INV>(v);
+      float2 *y = b + (j - k) * R + k;
+#pragma unroll
+      for (int t = 0; t < R; ++t) y[t * NS] = v[t];
+    }
+  }
+}
+
+__device__ inline void wave_fence() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The 360-point column line (the FFT grid of the 921 x 301 model) as
+// 8 x 9 x 5 with compile-time sizes; the radix order the host factors 360
+// into, so the result matches the generic path exactly.  Result in b.
+template <bool INV>
+__device__ void fft_wave_360(float2 *a, float2 *b, const float2 *tw) {
+  wave_stage_c<8, INV, 360, 1>(a, b, tw);
+  wave_fence();
+  wave_stage_c<9, INV, 360, 8>(b, a, tw);
+  wave_fence();
+  wave_stage_c<5, INV, 360, 72>(a, b, tw);
+  wave_fence();
+}
+
 __device__ inline void load_tw(float2 *dst, const Fft1 &f) {
   for (int i = threadIdx.x; i < f.n; i += blockDim.x) dst[i] = f.tw[i];
 }
@@ -361,6 +413,11 @@ __device__ const float2 *cols_fft(float2 *a, float2 *b, int pitch, int C, const 
                                   const float2 *tw) {
   if (C == CNT / 64) {
     const int w = threadIdx.x >> 6;
+    if (f.n == 360 && f.ns == 3 && f.radix[0] == 8 && f.radix[1] == 9 && f.radix[2] == 5) {
+      fft_wave_360<INV>(a + w * pitch, b + w * pitch, tw);
+      __syncthreads();
+      return b;
+    }
     const float2 *r = fft_wave<INV>(a + w * pitch, b + w * pitch, f, tw);
     __syncthreads();
     return r - w * pitch;  // the same buffer for every line (same stage count)
