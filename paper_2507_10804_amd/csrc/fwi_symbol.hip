@@ -681,6 +681,68 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_w(SymGeo g, const float2
 // form's five; the same workgroup and term-split structure as
 // k_rows_inv_blend_w.  Lane (n1, c) ends with the outputs x = n1 + 15 (c + 8 d).
 constexpr int BL_P = 68;
+constexpr int SPLIT_LDS = 960 + 64;  // the two twiddle tables, in float2
+
+// The twiddle tables of the split transform in LDS (every thread of the
+// workgroup takes part; the caller synchronises): T2[n1][k2] = w960^(n1 k2),
+// T3[c][b] = w64^(c b), conjugated for the inverse.
+template <bool INV>
+__device__ inline void split960_tables(const Fft1 &f, float2 *T2, float2 *T3) {
+  for (int i = threadIdx.x; i < 960; i += blockDim.x) {
+    const float2 t = f.tw[((i >> 6) * (i & 63)) % 960];
+    T2[i] = make_float2(t.x, INV ? -t.y : t.y);
+  }
+  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+    const float2 t = f.tw[15 * (i >> 3) * (i & 7)];
+    T3[i] = make_float2(t.x, INV ? -t.y : t.y);
+  }
+}
+
+// One 960-point line transformed by one wavefront, split as above: u holds
+// the lane's inputs x[64 k1 + lane], a is the wavefront's LDS line (15 rows
+// BL_P apart).  emit(it, n1, c, y) receives, for each of the lane's (n1, c)
+// pairs (pp = lane + 64 it < 120), the outputs y[d] = X[n1 + 15 (c + 8 d)].
+// Ends with a wavefront fence, so the line may be rewritten at once.
+template <bool INV, class Emit>
+__device__ inline void split960(float2 (&u)[15], float2 *a, const float2 *T2, const float2 *T3,
+                                Emit emit) {
+  const int lane = threadIdx.x & 63;
+  dft<15, INV>(u);
+#pragma unroll
+  for (int n1 = 0; n1 < 15; ++n1) a[n1 * BL_P + lane] = n1 ? cmul(u[n1], T2[n1 * 64 + lane]) : u[0];
+  wave_sync();
+  // the two halves of the pass touch disjoint rows (n1 < 8, n1 >= 8), so
+  // each reads, fences and writes on its own with 8 values in registers
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int pp = lane + 64 * it, n1 = pp >> 3, b = pp & 7;
+    float2 v8[8];
+    if (pp < 120) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v8[k] = a[n1 * BL_P + 8 * k + b];
+    }
+    wave_sync();
+    if (pp < 120) {
+      dft<8, INV>(v8);
+#pragma unroll
+      for (int c = 0; c < 8; ++c)
+        a[n1 * BL_P + 8 * c + (b ^ c)] = c ? cmul(v8[c], T3[c * 8 + b]) : v8[0];
+    }
+  }
+  wave_sync();
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
+    if (pp < 120) {
+      float2 v8[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v8[k] = a[n1 * BL_P + 8 * c + (k ^ c)];
+      dft<8, INV>(v8);
+      emit(it, n1, c, v8);
+    }
+  }
+  wave_sync();
+}
 
 __global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const float2 *__restrict__ z,
                                                            int T, int B, int S,
@@ -690,17 +752,8 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const floa
   constexpr int N = 960, LINE = 15 * BL_P;
   const int nz = g.nz, nx = g.nx;
   const int W = blockDim.x >> 6, w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float2 *T2 = sm;        // [n1][k2]: w960^(n1 k2)
-  float2 *T3 = sm + N;    // [c][b]: w64^(c b)
-  float2 *a = sm + N + 64 + w * LINE;
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    float2 t = g.fx.tw[((i >> 6) * (i & 63)) % N];
-    T2[i] = make_float2(t.x, -t.y);
-  }
-  for (int i = threadIdx.x; i < 64; i += blockDim.x) {
-    float2 t = g.fx.tw[15 * (i >> 3) * (i & 7)];
-    T3[i] = make_float2(t.x, -t.y);
-  }
+  float2 *T2 = sm, *T3 = sm + N, *a = sm + SPLIT_LDS + w * LINE;
+  split960_tables<true>(g.fx, T2, T3);
   __syncthreads();
   const int q = w / S, p = w - q * S;
   const int row = blockIdx.x, v = blockIdx.y * (W / S) + q;
@@ -715,49 +768,17 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const floa
     float2 u[15];
 #pragma unroll
     for (int k1 = 0; k1 < 15; ++k1) u[k1] = zr[64 * k1 + lane];
-    dft<15, true>(u);
-#pragma unroll
-    for (int n1 = 0; n1 < 15; ++n1) a[n1 * BL_P + lane] = n1 ? cmul(u[n1], T2[n1 * 64 + lane]) : u[0];
-    wave_sync();
-    // the two halves of the pass touch disjoint rows (n1 < 8, n1 >= 8), so
-    // each reads, fences and writes on its own with 8 values in registers
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int pp = lane + 64 * it, n1 = pp >> 3, b = pp & 7;
-      float2 v8[8];
-      if (pp < 120) {
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v8[k] = a[n1 * BL_P + 8 * k + b];
-      }
-      wave_sync();
-      if (pp < 120) {
-        dft<8, true>(v8);
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          a[n1 * BL_P + 8 * c + (b ^ c)] = c ? cmul(v8[c], T3[c * 8 + b]) : v8[0];
-      }
-    }
-    wave_sync();
     const float2 *Ar = A + ((long long)t * nz + row) * nx;
+    split960<true>(u, a, T2, T3, [&](int it, int n1, int c, const float2 (&y)[8]) {
 #pragma unroll
-    for (int it = 0; it < 2; ++it) {
-      const int pp = lane + 64 * it, n1 = pp >> 3, c = pp & 7;
-      if (pp < 120) {
-        float2 v8[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) v8[k] = a[n1 * BL_P + 8 * c + (k ^ c)];
-        dft<8, true>(v8);
-#pragma unroll
-        for (int d = 0; d < 8; ++d) {
-          const int x = n1 + 15 * (c + 8 * d);
-          if (x < nx) {
-            const float2 cf = Ar[x], y = v8[d];
-            acc[it][d] = fmaf(cf.x, y.x, fmaf(-cf.y, y.y, acc[it][d]));
-          }
+      for (int d = 0; d < 8; ++d) {
+        const int x = n1 + 15 * (c + 8 * d);
+        if (x < nx) {
+          const float2 cf = Ar[x];
+          acc[it][d] = fmaf(cf.x, y[d].x, fmaf(-cf.y, y[d].y, acc[it][d]));
         }
       }
-    }
-    wave_sync();  // the next term's writes come after these reads
+    });
   }
   if (S > 1) {  // uniform over the workgroup
     float *part = reinterpret_cast<float *>(a);  // 2 LINE floats >= nx
@@ -798,6 +819,34 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const floa
       if (pp < 120 && x < nx) o[x] = acc[it][d] * f;
     }
   }
+}
+
+// Forward row transforms of 960 points with the split transform of the
+// blend (forward sign): one wavefront per row, four rows per workgroup, the
+// real inputs loaded straight from global memory.  Rows in[row][cols] (zero
+// beyond cols), row = the flat index over the batch; out[row][960].
+__global__ __launch_bounds__(256) void k_rows_fwd_960(SymGeo g, const float *__restrict__ in,
+                                                     int nrows, int cols,
+                                                     float2 *__restrict__ out) {
+  extern __shared__ float2 sm[];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  float2 *T2 = sm, *T3 = sm + 960, *a = sm + SPLIT_LDS + w * 15 * BL_P;
+  split960_tables<false>(g.fx, T2, T3);
+  __syncthreads();
+  const long long row = (long long)blockIdx.x * (blockDim.x >> 6) + w;
+  if (row >= nrows) return;  // whole wavefront, after the only workgroup barrier
+  const float *src = in + row * cols;
+  float2 u[15];
+#pragma unroll
+  for (int k1 = 0; k1 < 15; ++k1) {
+    const int i = 64 * k1 + lane;
+    u[k1] = make_float2(i < cols ? src[i] : 0.0f, 0.0f);
+  }
+  float2 *dst = out + row * 960;
+  split960<false>(u, a, T2, T3, [&](int, int n1, int c, const float2 (&y)[8]) {
+#pragma unroll
+    for (int d = 0; d < 8; ++d) dst[n1 + 15 * (c + 8 * d)] = y[d];
+  });
 }
 
 // Inverse row transforms of z[0][t][row] and demodulation by the sample
@@ -1289,8 +1338,14 @@ ApplyLayout apply_layout(const fwi_symbol *s, int B, int T) {
 int forward(const fwi_symbol *s, const float *in, int rows, int cols, int B, float2 *rowt,
             float2 *spec, hipStream_t st) {
   const SymGeo &g = s->g;
-  hipLaunchKernelGGL(k_rows_fwd, dim3(rows, B), dim3(NTH), row_lds(g.mx), st, g, in, rows, cols,
-                     rowt);
+  if (g.mx == 960 && s->r960) {
+    const int nrows = rows * B;
+    hipLaunchKernelGGL(k_rows_fwd_960, dim3((nrows + 3) / 4), dim3(256),
+                       sizeof(float2) * (SPLIT_LDS + 4 * 15 * BL_P), st, g, in, nrows, cols, rowt);
+  } else {
+    hipLaunchKernelGGL(k_rows_fwd, dim3(rows, B), dim3(NTH), row_lds(g.mx), st, g, in, rows, cols,
+                       rowt);
+  }
   SY_TRY(hipGetLastError());
   const int cs = col_band(g.mz), C = 1 << cs;
   hipLaunchKernelGGL(k_cols_fwd, dim3(band_grid(g.mx, C), B), dim3(CNT), col_lds(g.mz, cs), st, g,
