@@ -57,6 +57,7 @@ GRIDS = [
     (1, 7, 1, 8, 2),           # one row, trivial column transforms
     (13, 1, 15, 1, 6),         # one column
     (301, 921, 360, 960, 8),   # the 921 x 301 model with a 31-cell padding
+    (4, 700, 6, 720, 4),       # rows in (512, 1024] other than 960: the generic 1024-point blend
     (3, 1500, 4, 1536, 4),     # rows above 1024 points
     (2, 2000, 2, 2048, 2),     # the longest rows
 ]
