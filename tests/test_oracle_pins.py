@@ -257,9 +257,9 @@ def test_hessian_zero_residual_identity():
 
 
 def test_shot_sum_and_batch():
-    """H_d sums per-source contributions ("two wave equations per source",
-    Section 3): H v over all shots equals the sum of single-shot products,
-    and a batch of vectors equals one call per vector."""
+    """H_d sums per-source contributions (two wave solves per source, Section
+    3): H v over all shots equals the sum of single-shot products, and a
+    batch of vectors equals one call per vector."""
     g, m, v = _setup(nt=150)
     u = synth.smooth_random(m.shape, seed=9, sigma=3.0)
     full = oracle.gn_hvp(g, m, v)
