@@ -494,16 +494,45 @@ __global__ __launch_bounds__(CNT) void k_cols_inv(SymGeo g, const float2 *__rest
   const int col0 = band * C;
   const long long t = blockIdx.y, bv = blockIdx.z;
   const __amdgpu_buffer_rsrc_t rS = brsrc(spec + bv * n * mx), rW = brsrc(Mt + t * n * mx);
-  staged<4, CNT>(n * C,
-            [&](int e) {
-              const int i = e >> cs, c = e & (C - 1);
-              if (col0 + c >= mx) return make_float2(0.0f, 0.0f);
-              const int o = (i * mx + col0 + c) << 3;
-              return cmul(bld2(rS, o), bld2(rW, o));
-            },
-            [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
-  __syncthreads();
-  const float2 *res = cols_fft<true>(a, b, pitch, C, g.fz, tw);
+  const float2 *res;
+  if (n == 360 && C == CNT / 64 && g.fz.ns == 3 && g.fz.radix[0] == 8 && g.fz.radix[1] == 9 &&
+      g.fz.radix[2] == 5) {
+    // 360-point lines: thread (column c, butterfly j < 45) loads its radix-8
+    // inputs, rows j + 45 t, straight from global memory and writes the first
+    // Stockham stage's outputs 8 j + t (the same values in the same order as
+    // staging the products and running that stage from LDS, one LDS round
+    // trip less); the wavefronts then run stages 9 and 5 on their columns.
+    const int c = threadIdx.x & (CNT / 64 - 1), j = threadIdx.x / (CNT / 64);
+    if (j < 45) {
+      float2 v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int o = ((j + 45 * k) * mx + col0 + c) << 3;
+        v[k] = col0 + c < mx ? cmul(bld2(rS, o), bld2(rW, o)) : make_float2(0.0f, 0.0f);
+      }
+      dft<8, true>(v);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) b[c * pitch + 8 * j + k] = v[k];
+    }
+    __syncthreads();  // a column's first stage came from several wavefronts; the twiddles
+    const int w = threadIdx.x >> 6;
+    wave_stage_c<9, true, 360, 8>(b + w * pitch, a + w * pitch, tw);
+    wave_fence();
+    wave_stage_c<5, true, 360, 72>(a + w * pitch, b + w * pitch, tw);
+    __syncthreads();
+    res = b;
+  } else {
+    staged<4, CNT>(n * C,
+              [&](int e) {
+                const int i = e >> cs, c = e & (C - 1);
+                if (col0 + c >= mx) return make_float2(0.0f, 0.0f);
+                const int o = (i * mx + col0 + c) << 3;
+                return cmul(bld2(rS, o), bld2(rW, o));
+              },
+              [&](int e, float2 v) { a[(e & (C - 1)) * pitch + (e >> cs)] = v; });
+    __syncthreads();
+    res = cols_fft<true>(a, b, pitch, C, g.fz, tw);
+  }
   // streaming stores: the partial transforms are read once, by the next pass;
   // allocating them in L2 would evict the table and spectrum bands that the
   // other vectors' and terms' workgroups re-read
