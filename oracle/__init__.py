@@ -10,8 +10,11 @@ polynomial exactness of the Laplacian, the analytic 2-D Green's function
 and its convergence order, discrete reciprocity, the adjoint dot-product
 identity, finite-difference derivative checks, Hessian symmetry / PSD /
 zero-residual identity, and brute-force dense Jacobians on tiny grids.  The
-absorbing-sponge profile is a chosen convention: its parity is unpinned by
-the paper (only a reflection-size and energy-decay sanity check applies).
+absorbing sponge is a chosen convention (the paper fixes no boundary
+treatment); it is pinned to the normal-incidence reflection of the
+continuous damped wave equation off the same layer (a frequency-domain ODE
+solve), to the additivity of the two axes' damping in the corners, and to
+energy decay.
 """
 from __future__ import annotations
 
