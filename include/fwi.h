@@ -127,6 +127,37 @@ int fwi_plan_bind(fwi_plan *p, void *dev, size_t bytes, void *stream);
  * FORWARD / MISFIT_GRAD).  Workspaces must be 256-byte aligned. */
 int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes);
 
+/* Tuning options of a plan: how the time loops are split into kernel
+ * launches.  None changes what is computed; options marked (*) change the
+ * order of FP32 additions in the images, so results can differ in the last
+ * bits between settings (every setting is deterministic).  Defaults are the
+ * fastest measured on MI355X for the workloads of this library.  Changing an
+ * option can change fwi_workspace_size: query it again afterwards. */
+enum {
+  FWI_OPT_TWO_STEP_FORWARD = 0, /* 0/1: forward and recompute kernels advance two time
+                                   steps per launch (default 0; needs an even K) */
+  FWI_OPT_TWO_STEP_BORN = 1,    /* 0/1: the same for forward + Born (default 1) */
+  FWI_OPT_TWO_STEP_ADJOINT = 2, /* 0/1: the same for the adjoint (default 1) (*) */
+  FWI_OPT_ADJ_VECTORS = 3,      /* right-hand sides per two-step adjoint workgroup,
+                                   1..4; 0 (default): pairs for even counts, fours for
+                                   odd counts of 5 or more */
+  FWI_OPT_ADJ_SHOT_GROUP = 4,   /* shots summed per adjoint workgroup; 0 (default):
+                                   the largest power of two <= 16 that keeps >= 4096
+                                   workgroups (*) */
+  FWI_OPT_STEP_ORDER = 5,       /* workgroup order of the one-step forward kernels:  */
+  FWI_OPT_BORN_ORDER = 6,       /*   0 shot-major (default), 1 tile-major, 2 blocked */
+  FWI_OPT_ADJ_ORDER = 7,        /* the same for the one-step adjoint                  */
+  FWI_OPT_BLOCK_X = 8,          /* tiles per block of the blocked order, 1..64 (default 2); */
+  FWI_OPT_BLOCK_Z = 9,          /*   set before fwi_plan_bind                               */
+  FWI_OPT_COUNT = 10
+};
+
+/* Set option `option` to `value`.  FWI_EINVAL for an unknown option, a value
+ * out of range, or a block size after fwi_plan_bind.  Takes effect from the
+ * next compute call; not while a call on this plan is still being enqueued. */
+int fwi_plan_set_option(fwi_plan *p, int option, int value);
+int fwi_plan_get_option(const fwi_plan *p, int option, int *value);
+
 /* Padded-grid geometry the kernels use (for tools and tests):
  * dims[0..5] = NZp, NXp, row pitch (floats), tile rows, tile columns, K. */
 int fwi_plan_dims(const fwi_plan *p, int32_t dims[6]);

@@ -86,6 +86,21 @@ typedef struct fwi_symbol fwi_symbol;
 int fwi_symbol_check(const fwi_symbol_grid *g);
 int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out);
 void fwi_symbol_destroy(fwi_symbol *s);
+/* Tuning options of a symbol object (none changes what is computed; the
+ * blend split changes the order of FP32 additions over the terms).  Defaults
+ * are the fastest measured on MI355X. */
+enum {
+  FWI_SYM_OPT_CHUNK_MB = 0,    /* MiB of partial transforms per vector chunk of an
+                                  apply, >= 1 (default 4096) */
+  FWI_SYM_OPT_BLEND_SPLIT = 1, /* wavefronts sharing one vector's terms in the inverse
+                                  row blend, 1..4 (must divide the wavefronts per
+                                  workgroup, else 1); 0 (default): by grid size */
+  FWI_SYM_OPT_SPLIT_960 = 2    /* 0/1: 960-point rows by the split 15 x 64 transform
+                                  (default 1) */
+};
+/* FWI_EINVAL for an unknown option or a value out of range. */
+int fwi_symbol_set_option(fwi_symbol *s, int option, int value);
+int fwi_symbol_get_option(const fwi_symbol *s, int option, int *value);
 /* Bytes of the device block (FFT twiddle tables). */
 int fwi_symbol_device_bytes(const fwi_symbol *s, size_t *bytes);
 /* Copy the tables into `dev` (256-byte aligned) and synchronise `stream`. */

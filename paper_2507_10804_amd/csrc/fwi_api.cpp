@@ -67,9 +67,11 @@ struct fwi_plan {
   size_t off_status = 0, off_src = 0, off_trp = 0, off_rloc = 0, off_rid = 0, off_tnp = 0,
          off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0, off_order = 0;
   size_t off2[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // two-step tables
-  // advance two time steps per launch (needs K even), per kernel family;
-  // defaults from measurement: the Born and adjoint kernels gain, the plain
-  // forward does not
+  // requested options (fwi_plan_set_option), indexed by FWI_OPT_*
+  int opt[FWI_OPT_COUNT] = {0, 1, 1, 0, 0, 0, 0, 0, 2, 2};
+  // advance two time steps per launch, per kernel family: the requested
+  // option where K is even (the checkpoint levels must fall on launch
+  // boundaries), else single steps
   bool ts_fwd = false, ts_born = true, ts_adj = true;
   // vectors per two-step adjoint workgroup (1..4; 0 = by batch): pairs for
   // even batches; for odd batches of 5 or more (the fused gradient + B
@@ -77,6 +79,17 @@ struct fwi_plan {
   // instead of a lone vector in a pair's slot (measured: B + 1 = 17 runs 7 %
   // faster with fours than with pairs, B = 16 3 % slower)
   int adj_pair = 0;
+  void apply_options() {
+    const bool even = K % 2 == 0;
+    ts_fwd = even && opt[FWI_OPT_TWO_STEP_FORWARD];
+    ts_born = even && opt[FWI_OPT_TWO_STEP_BORN];
+    ts_adj = even && opt[FWI_OPT_TWO_STEP_ADJOINT];
+    adj_pair = opt[FWI_OPT_ADJ_VECTORS];
+    adj_group_override = opt[FWI_OPT_ADJ_SHOT_GROUP];
+    step_order = opt[FWI_OPT_STEP_ORDER];
+    born_order = opt[FWI_OPT_BORN_ORDER];
+    adj_order = opt[FWI_OPT_ADJ_ORDER];
+  }
   int adj_nb(int B) const {
     if (adj_pair > 0) return std::min(adj_pair, B);
     if (B % 2 == 0) return 2;
@@ -380,11 +393,60 @@ int prologue(fwi_plan *p, const Layout &L, void *ws, const float *m, const float
   return FWI_OK;
 }
 
+// Blocked workgroup order of the one-step kernels: rectangles of
+// FWI_OPT_BLOCK_X x FWI_OPT_BLOCK_Z tiles, row by row, written into the
+// plan's device-block image.
+void build_order(fwi_plan *p) {
+  Geo &g = p->geo;
+  const int bx = p->opt[FWI_OPT_BLOCK_X], bz = p->opt[FWI_OPT_BLOCK_Z];
+  int *order = p->blk.data() + p->off_order;
+  int q = 0;
+  for (int z0 = 0; z0 < g.tiles_z; z0 += bz)
+    for (int x0 = 0; x0 < g.tiles_x; x0 += bx)
+      for (int z = z0; z < std::min(z0 + bz, g.tiles_z); ++z)
+        for (int x = x0; x < std::min(x0 + bx, g.tiles_x); ++x) order[q++] = z * g.tiles_x + x;
+  g.blk = bx * bz;
+  g.nblocks = (g.ntiles + g.blk - 1) / g.blk;
+}
+
 }  // namespace
 
 extern "C" {
 
 int fwi_abi_version(void) { return FWI_ABI_VERSION; }
+
+int fwi_plan_set_option(fwi_plan *p, int option, int value) {
+  if (!p) return fail(FWI_EINVAL, "null plan");
+  if (option < 0 || option >= FWI_OPT_COUNT) return fail(FWI_EINVAL, "unknown option");
+  int lo = 0, hi = 0;
+  switch (option) {
+    case FWI_OPT_TWO_STEP_FORWARD:
+    case FWI_OPT_TWO_STEP_BORN:
+    case FWI_OPT_TWO_STEP_ADJOINT: hi = 1; break;
+    case FWI_OPT_ADJ_VECTORS: hi = 4; break;
+    case FWI_OPT_ADJ_SHOT_GROUP: hi = 65536; break;
+    case FWI_OPT_STEP_ORDER:
+    case FWI_OPT_BORN_ORDER:
+    case FWI_OPT_ADJ_ORDER: hi = 2; break;
+    default: lo = 1; hi = 64; break;  // block sizes
+  }
+  if (value < lo || value > hi)
+    return fail(FWI_EINVAL, "option " + std::to_string(option) + " takes values in [" +
+                                std::to_string(lo) + ", " + std::to_string(hi) + "]");
+  if ((option == FWI_OPT_BLOCK_X || option == FWI_OPT_BLOCK_Z) && p->dev)
+    return fail(FWI_EINVAL, "block sizes must be set before fwi_plan_bind");
+  p->opt[option] = value;
+  p->apply_options();
+  if (option == FWI_OPT_BLOCK_X || option == FWI_OPT_BLOCK_Z) build_order(p);
+  return FWI_OK;
+}
+
+int fwi_plan_get_option(const fwi_plan *p, int option, int *value) {
+  if (!p || !value) return fail(FWI_EINVAL, "null argument");
+  if (option < 0 || option >= FWI_OPT_COUNT) return fail(FWI_EINVAL, "unknown option");
+  *value = p->opt[option];
+  return FWI_OK;
+}
 
 const char *fwi_strerror(int code) {
   switch (code) {
@@ -464,11 +526,6 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   p->nseg = (G.nt - 1 + p->K - 1) / p->K;
   p->inv_noise_var = G.inv_noise_var;
   p->wavelet.assign(G.wavelet, G.wavelet + G.nt);
-  // tuning knobs for experiments; the defaults are the measured best
-  if (const char *e = std::getenv("FWI_ADJ_GROUP")) p->adj_group_override = std::atoi(e);
-  if (const char *e = std::getenv("FWI_STEP_ORDER")) p->step_order = std::atoi(e);
-  if (const char *e = std::getenv("FWI_BORN_ORDER")) p->born_order = std::atoi(e);
-  if (const char *e = std::getenv("FWI_ADJ_ORDER")) p->adj_order = std::atoi(e);
 
   // receiver tables: sort receivers by (tile, local index, number)
   std::vector<std::tuple<int, int, int, long long>> recs;  // tile, local, id, gidx
@@ -528,18 +585,9 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   p->off_ngidx = put(ngidx);
   p->off_nrp = put(nrp);
   p->off_nrec = put(nrec);
-  // blocked workgroup order: bx x bz rectangles of tiles, row by row
-  int bx = 2, bz = 2;
-  if (const char *e = std::getenv("FWI_BLOCK_X")) bx = std::max(1, std::atoi(e));
-  if (const char *e = std::getenv("FWI_BLOCK_Z")) bz = std::max(1, std::atoi(e));
-  std::vector<int> order;
-  for (int z0 = 0; z0 < g.tiles_z; z0 += bz)
-    for (int x0 = 0; x0 < g.tiles_x; x0 += bx)
-      for (int z = z0; z < std::min(z0 + bz, g.tiles_z); ++z)
-        for (int x = x0; x < std::min(x0 + bx, g.tiles_x); ++x) order.push_back(z * g.tiles_x + x);
-  g.blk = bx * bz;
-  g.nblocks = (g.ntiles + g.blk - 1) / g.blk;
-  p->off_order = put(order);
+  // blocked workgroup order (rebuilt by fwi_plan_set_option before binding)
+  p->off_order = put(std::vector<int>(g.ntiles, 0));
+  build_order(p);
 
   // two-step tiling and its receiver tables
   g.tiles_x2 = (int)((nxp + TX2 - 1) / TX2);
@@ -591,19 +639,7 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
     p->off2[6] = put(nrp2);
     p->off2[7] = put(nrec2);
   }
-  // FWI_TWO_STEP: three 0/1 digits for forward, Born, adjoint (tuning knob)
-  if (const char *e = std::getenv("FWI_TWO_STEP")) {
-    const std::string f(e);
-    if (f.size() == 3) {
-      p->ts_fwd = f[0] == '1';
-      p->ts_born = f[1] == '1';
-      p->ts_adj = f[2] == '1';
-    } else {
-      p->ts_fwd = p->ts_born = p->ts_adj = std::atoi(e) != 0;
-    }
-  }
-  if (p->K % 2) p->ts_fwd = p->ts_born = p->ts_adj = false;
-  if (const char *e = std::getenv("FWI_ADJ_PAIR")) p->adj_pair = std::max(1, std::min(4, std::atoi(e)));
+  p->apply_options();
   *out = p;
   return FWI_OK;
 }

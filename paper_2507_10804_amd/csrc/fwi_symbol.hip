@@ -1399,15 +1399,42 @@ extern "C" {
 
 int fwi_symbol_check(const fwi_symbol_grid *g) { return check_grid(g); }
 
+int fwi_symbol_set_option(fwi_symbol *s, int option, int value) {
+  if (!s) return set_error(FWI_EINVAL, "null symbol");
+  switch (option) {
+    case FWI_SYM_OPT_CHUNK_MB:
+      if (value < 1 || value > (1 << 20)) return set_error(FWI_EINVAL, "chunk must be in [1, 2^20] MiB");
+      s->zchunk = (size_t)value << 20;
+      return FWI_OK;
+    case FWI_SYM_OPT_BLEND_SPLIT:
+      if (value < 0 || value > 4) return set_error(FWI_EINVAL, "blend split must be in [0, 4]");
+      s->split = value;
+      return FWI_OK;
+    case FWI_SYM_OPT_SPLIT_960:
+      if (value < 0 || value > 1) return set_error(FWI_EINVAL, "960-point split must be 0 or 1");
+      s->r960 = value;
+      return FWI_OK;
+    default:
+      return set_error(FWI_EINVAL, "unknown symbol option");
+  }
+}
+
+int fwi_symbol_get_option(const fwi_symbol *s, int option, int *value) {
+  if (!s || !value) return set_error(FWI_EINVAL, "null argument");
+  switch (option) {
+    case FWI_SYM_OPT_CHUNK_MB: *value = (int)(s->zchunk >> 20); return FWI_OK;
+    case FWI_SYM_OPT_BLEND_SPLIT: *value = s->split; return FWI_OK;
+    case FWI_SYM_OPT_SPLIT_960: *value = s->r960; return FWI_OK;
+    default: return set_error(FWI_EINVAL, "unknown symbol option");
+  }
+}
+
 int fwi_symbol_create(const fwi_symbol_grid *g, fwi_symbol **out) {
   if (!out) return set_error(FWI_EINVAL, "null argument");
   *out = nullptr;
   if (int rc = check_grid(g)) return rc;
   fwi_symbol *s = new fwi_symbol;
   s->gi = *g;
-  if (const char *e = std::getenv("FWI_SYM_ZCHUNK_MB")) s->zchunk = (size_t)std::max(1, std::atoi(e)) << 20;
-  if (const char *e = std::getenv("FWI_SYM_SPLIT")) s->split = std::max(0, std::min(4, std::atoi(e)));
-  if (const char *e = std::getenv("FWI_SYM_R960")) s->r960 = std::atoi(e) != 0;
   SymGeo &G = s->g;
   G.nz = g->nz;
   G.nx = g->nx;

@@ -37,8 +37,15 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_pdo_weights", "fwi_pdo_masks", "fwi_pdo_workspace_size", "fwi_pdo_columns",
            "fwi_psfplus_workspace_size", "fwi_psfplus_build", "fwi_vec_workspace_size",
            "fwi_vec_dot", "fwi_vec_update", "fwi_lbfgs_pair", "fwi_lbfgs_loop1",
-           "fwi_lbfgs_loop2"]
+           "fwi_lbfgs_loop2", "fwi_plan_set_option", "fwi_plan_get_option",
+           "fwi_symbol_set_option", "fwi_symbol_get_option"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
+# plan options (include/fwi.h, FWI_OPT_*)
+OPTIONS = {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 2,
+           "adj_vectors": 3, "adj_shot_group": 4, "step_order": 5, "born_order": 6,
+           "adj_order": 7, "block_x": 8, "block_z": 9}
+# symbol options (include/fwi_symbol.h, FWI_SYM_OPT_*)
+SYMBOL_OPTIONS = {"chunk_mb": 0, "blend_split": 1, "split_960": 2}
 
 
 class FwiError(RuntimeError):
@@ -128,6 +135,10 @@ def load_library(path: str = LIB_PATH):
             "fwi_lbfgs_pair": ([L, P, P, P, P, P, Z, P], I),
             "fwi_lbfgs_loop1": ([L, I, P, P, P, P, P, P, P, Z, P], I),
             "fwi_lbfgs_loop2": ([L, I, P, P, P, P, P, P, P, Z, P], I),
+            "fwi_plan_set_option": ([P, I, I], I),
+            "fwi_plan_get_option": ([P, I, P], I),
+            "fwi_symbol_set_option": ([P, I, I], I),
+            "fwi_symbol_get_option": ([P, I, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -162,10 +173,12 @@ class Plan:
     data space [B][ns][nt][nr]) and enqueue on the current torch stream.
     Workspaces are cached per (operation, batch) unless the caller passes its
     own (``ws=``).  Calls from several threads on different streams are safe
-    when each brings its own workspace and telemetry is off.
+    when each brings its own workspace and telemetry is off.  ``options``
+    maps names of :data:`OPTIONS` to values (the plan's tuning options, set
+    before the device block is bound).
     """
 
-    def __init__(self, geom, device=None):
+    def __init__(self, geom, device=None, options=None):
         import torch
 
         self.torch = torch
@@ -176,6 +189,9 @@ class Plan:
         h = ctypes.c_void_p()
         _check(self.lib.fwi_plan_create(ctypes.byref(g), ctypes.byref(h)))
         self._h = h
+        self._ws = {}
+        for name, value in (options or {}).items():
+            self.set_option(name, value)
         nb = ctypes.c_size_t()
         _check(self.lib.fwi_plan_device_bytes(h, ctypes.byref(nb)))
         self._blk = torch.zeros(max(nb.value, 256), dtype=torch.uint8, device=self.device)
@@ -195,6 +211,19 @@ class Plan:
 
     def _stream(self):
         return ctypes.c_void_p(self.torch.cuda.current_stream(self.device).cuda_stream)
+
+    def set_option(self, name, value):
+        """Set a tuning option (a name of :data:`OPTIONS`); drops the cached
+        workspaces, whose size may change."""
+        if name not in OPTIONS:
+            raise KeyError(f"unknown plan option {name!r}")
+        _check(self.lib.fwi_plan_set_option(self._h, OPTIONS[name], int(value)))
+        self._ws = {}
+
+    def get_option(self, name):
+        v = ctypes.c_int()
+        _check(self.lib.fwi_plan_get_option(self._h, OPTIONS[name], ctypes.byref(v)))
+        return v.value
 
     def workspace_bytes(self, op, batch=1):
         n = ctypes.c_size_t()

@@ -44,7 +44,7 @@ def check(g: "synth.SymbolGrid") -> None:
 class Symbol:
     """FFT grid and sampling of the symbol approximations."""
 
-    def __init__(self, g: "synth.SymbolGrid", device=None):
+    def __init__(self, g: "synth.SymbolGrid", device=None, options=None):
         import torch
 
         self.torch = torch
@@ -55,6 +55,8 @@ class Symbol:
         h = ctypes.c_void_p()
         fwi._check(self.lib.fwi_symbol_create(ctypes.byref(self._gc), ctypes.byref(h)))
         self._h = h
+        for name, value in (options or {}).items():
+            self.set_option(name, value)
         nb = ctypes.c_size_t()
         fwi._check(self.lib.fwi_symbol_device_bytes(h, ctypes.byref(nb)))
         self._blk = torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device)
@@ -66,6 +68,12 @@ class Symbol:
         if h is not None and h.value:
             self.lib.fwi_symbol_destroy(h)
             self._h = None
+
+    def set_option(self, name, value):
+        """Set a tuning option (a name of ``fwi.SYMBOL_OPTIONS``)."""
+        if name not in fwi.SYMBOL_OPTIONS:
+            raise KeyError(f"unknown symbol option {name!r}")
+        fwi._check(self.lib.fwi_symbol_set_option(self._h, fwi.SYMBOL_OPTIONS[name], int(value)))
 
     def _st(self):
         return _stream(self.torch, self.device)

@@ -192,3 +192,52 @@ def test_psfplus_and_vector_validation(lib):
     assert lib.fwi_lbfgs_loop2(1000, 1, bad, fake, fake, fake, fake, fake, fake, n.value,
                                None) == -1
     assert lib.fwi_vec_dot(1000, fake, fake, fake, fake, n.value - 8, None) == -3
+
+
+def test_plan_options(lib):
+    """Tuning options live in the ABI: defaults readable, ranges enforced,
+    block sizes only before binding, and the two-step switches change the
+    workspace layout (two field sets) but nothing else."""
+    geom, _, _ = synth.config_small()
+    rc, h, _ = _plan(lib, geom)
+    assert rc == 0
+    v = ctypes.c_int()
+    defaults = {}
+    for name, opt in fwi.OPTIONS.items():
+        assert lib.fwi_plan_get_option(h, opt, ctypes.byref(v)) == 0
+        defaults[name] = v.value
+    assert defaults == {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 1,
+                        "adj_vectors": 0, "adj_shot_group": 0, "step_order": 0,
+                        "born_order": 0, "adj_order": 0, "block_x": 2, "block_z": 2}
+    for opt, bad in [(fwi.OPTIONS["two_step_born"], 2), (fwi.OPTIONS["adj_vectors"], 5),
+                     (fwi.OPTIONS["step_order"], -1), (fwi.OPTIONS["block_x"], 0),
+                     (fwi.OPTIONS["block_z"], 65), (10, 0), (-1, 0)]:
+        assert lib.fwi_plan_set_option(h, opt, bad) == -1
+    n_two, n_one = ctypes.c_size_t(), ctypes.c_size_t()
+    assert lib.fwi_workspace_size(h, fwi.FWI_OP_GN_HVP, 4, ctypes.byref(n_two)) == 0
+    for name in ("two_step_born", "two_step_adjoint"):
+        assert lib.fwi_plan_set_option(h, fwi.OPTIONS[name], 0) == 0
+    assert lib.fwi_workspace_size(h, fwi.FWI_OP_GN_HVP, 4, ctypes.byref(n_one)) == 0
+    assert n_one.value < n_two.value
+    steps = ctypes.c_int32()
+    assert lib.fwi_kernel_steps(h, fwi.KERNEL_ADJOINT, ctypes.byref(steps)) == 0
+    assert steps.value == 1
+    assert lib.fwi_plan_set_option(h, fwi.OPTIONS["block_x"], 4) == 0
+    assert lib.fwi_plan_get_option(h, fwi.OPTIONS["block_x"], ctypes.byref(v)) == 0
+    assert v.value == 4
+    lib.fwi_plan_destroy(h)
+    # an odd checkpoint interval keeps every kernel at one step per launch
+    geom.ckpt_every = 7
+    rc, h, _ = _plan(lib, geom)
+    assert lib.fwi_plan_set_option(h, fwi.OPTIONS["two_step_forward"], 1) == 0
+    for kind in (fwi.KERNEL_STEP, fwi.KERNEL_STEP_BORN, fwi.KERNEL_ADJOINT):
+        assert lib.fwi_kernel_steps(h, kind, ctypes.byref(steps)) == 0 and steps.value == 1
+    lib.fwi_plan_destroy(h)
+
+
+def test_no_environment_knobs():
+    """No source of the library reads the process environment."""
+    csrc = os.path.join(ROOT, "paper_2507_10804_amd", "csrc")
+    for name in os.listdir(csrc):
+        if name.endswith((".hip", ".cpp", ".h")):
+            assert "getenv" not in open(os.path.join(csrc, name)).read(), name

@@ -43,9 +43,9 @@ def host(x):
     return x.detach().double().cpu().numpy()
 
 
-def make_plan(geom):
+def make_plan(geom, options=None):
     from paper_2507_10804_amd import fwi
-    return fwi.Plan(geom)
+    return fwi.Plan(geom, options=options)
 
 
 # ------------------------------------------------------------ small config
@@ -214,19 +214,17 @@ def test_two_step_matches_one_step_data(torch, small):
 
 
 def _plan_with(geom, flags):
-    import os
-    os.environ["FWI_TWO_STEP"] = flags
-    try:
-        return make_plan(geom)
-    finally:
-        del os.environ["FWI_TWO_STEP"]
+    """Plan whose forward, Born and adjoint kernels advance one (0) or two (1)
+    steps per launch, flags in that order."""
+    names = ("two_step_forward", "two_step_born", "two_step_adjoint")
+    return make_plan(geom, options={n: int(f) for n, f in zip(names, flags)})
 
 
 def test_two_step_every_kernel(torch):
     """Every kernel family in its two-step form (forward, Born, adjoint with
     receiver injection in the halo ring) against the one-step forms and the
     oracle, on ragged tiles with receivers near tile edges."""
-    say("case: FWI_TWO_STEP=111 vs 000, ragged grid")
+    say("case: two-step kernels (111) vs one-step (000), ragged grid")
     g, m = tiny(nx=150, nz=50, nt=151, nb=10)
     ix = np.array([53, 54, 54, 45, 46, 101, 102, 0, 149])
     g.rec_zx = np.stack([np.array([1, 1, 1, 21, 22, 22, 20, 49, 0]), ix], 1).astype(np.int32)

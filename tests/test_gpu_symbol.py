@@ -91,7 +91,6 @@ def test_apply_blend_splits(split):
     """The blend with 1, 2 or 4 wavefronts sharing one vector's terms (the
     size rule picks 1 only for large batches): each against the oracle, on a
     batch that leaves wavefronts idle in the last workgroup."""
-    import os
 
     import torch
     from paper_2507_10804_amd import symbol as S
@@ -102,12 +101,8 @@ def test_apply_blend_splits(split):
     A = r32(rng.standard_normal((T, 30, 50)) + 1j * rng.standard_normal((T, 30, 50)))
     M = r32(rng.standard_normal((T, 32, 54)) + 1j * rng.standard_normal((T, 32, 54)))
     v = r32(rng.standard_normal((B, 30, 50)))
-    say(f"case: fwi_symbol_apply 30x50 on 32x54, T={T}, B={B}, FWI_SYM_SPLIT={split}")
-    os.environ["FWI_SYM_SPLIT"] = str(split)
-    try:
-        sym = S.Symbol(G)
-    finally:
-        del os.environ["FWI_SYM_SPLIT"]
+    say(f"case: fwi_symbol_apply 30x50 on 32x54, T={T}, B={B}, blend split {split}")
+    sym = S.Symbol(G, options={"blend_split": split})
     got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 0.5,
                          dev(torch, v)))
     for b in range(B):
@@ -119,7 +114,6 @@ def test_apply_960_point_rows(split):
     """Rows of 960 points take the 15 x 64 split transform: against the oracle
     with 1, 2 and 4 wavefronts per vector, T odd, B leaving wavefronts idle,
     and model rows ending inside the last radix-8 group (nx = 921)."""
-    import os
 
     import torch
     from paper_2507_10804_amd import symbol as S
@@ -130,12 +124,8 @@ def test_apply_960_point_rows(split):
     A = r32(rng.standard_normal((T, 6, 921)) + 1j * rng.standard_normal((T, 6, 921)))
     M = r32(rng.standard_normal((T, 8, 960)) + 1j * rng.standard_normal((T, 8, 960)))
     v = r32(rng.standard_normal((B, 6, 921)))
-    say(f"case: fwi_symbol_apply 6x921 on 8x960, T={T}, B={B}, FWI_SYM_SPLIT={split}")
-    os.environ["FWI_SYM_SPLIT"] = str(split)
-    try:
-        sym = S.Symbol(G)
-    finally:
-        del os.environ["FWI_SYM_SPLIT"]
+    say(f"case: fwi_symbol_apply 6x921 on 8x960, T={T}, B={B}, blend split {split}")
+    sym = S.Symbol(G, options={"blend_split": split})
     got = host(sym.apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64), 2.0,
                          dev(torch, v)))
     for b in range(B):
