@@ -10,6 +10,9 @@ tolerance, 1e-4, is far above float32 storage rounding).
   python tests/golden/make_full_size.py forward   # ~1 min, 10.5 GB RAM
   python tests/golden/make_full_size.py adjoint   # ~3 min
   python tests/golden/make_full_size.py hvp       # ~4 min
+  python tests/golden/make_full_size.py born      # ~2 min
+  python tests/golden/make_full_size.py grad      # ~5 min
+  python tests/golden/make_full_size.py probe     # ~8 min (two products)
 """
 import json
 import os
@@ -50,6 +53,27 @@ def main(what):
         v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
         hv = oracle.gn_hvp(g, m_eval, v)
         np.savez_compressed(out, hv=hv.astype(np.float32), shot=SHOT, v_seed=1)
+    elif what == "born":
+        v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
+        dd = oracle.born(g, m_eval, v)[0]
+        np.savez_compressed(out, dd=dd[::T_STRIDE, ::REC_STRIDE].astype(np.float32),
+                            rec_stride=REC_STRIDE, t_stride=T_STRIDE, shot=SHOT, v_seed=1)
+    elif what == "grad":
+        # observed data: the noise-free forward map of the true model
+        dobs = oracle.forward(g, m_true)
+        phi, grad = oracle.misfit_grad(g, m_eval, dobs)
+        np.savez_compressed(out, grad=grad.astype(np.float32), phi=np.float64(phi), shot=SHOT)
+    elif what == "probe":
+        # the two probe families of a batched-probing launch: an impulse comb
+        # (deltas every 40 cells, first member of the seed-100 set) and a
+        # Rademacher field smoothed over 5 cells (seed 200)
+        comb = synth.impulse_combs(g.nz, g.nx, count=64, spacing=40, seed=100)[0]
+        rad = synth.rademacher_smoothed(g.nz, g.nx, seeds=[200], sigma=5.0)[0]
+        hv_comb = oracle.gn_hvp(g, m_eval, comb)
+        hv_rad = oracle.gn_hvp(g, m_eval, rad)
+        np.savez_compressed(out, hv_comb=hv_comb.astype(np.float32),
+                            hv_rad=hv_rad.astype(np.float32), shot=SHOT, comb_seed=100,
+                            comb_member=0, rad_seed=200)
     else:
         raise SystemExit(f"unknown fixture {what}")
     print(json.dumps({"fixture": what, "seconds": time.time() - t0}))

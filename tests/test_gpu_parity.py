@@ -178,6 +178,46 @@ def test_fused_grad_hvp_matches_separate_calls(torch, small):
     assert p.status() == 0
 
 
+_FUSED_REF = {}
+
+
+def _fused_reference(small, B):
+    """Oracle Phi, gradient and the B products of the fused-call tests, at a
+    model 5 % faster than the truth (a residual comparable to the data, so
+    the gradient is held to the image tolerance)."""
+    if B not in _FUSED_REF:
+        g, m = small["g"], 1.05 * small["m_true"]
+        vs = synth.smooth_random_batch(g.nz, g.nx, seeds=range(31, 31 + B))
+        phi, grad = oracle.misfit_grad(g, m, small["dobs"])
+        _FUSED_REF[B] = (m, vs, phi, grad, oracle.gn_hvp(g, m, vs))
+    return _FUSED_REF[B]
+
+
+@pytest.mark.parametrize("B", [4, 6, 16])
+@pytest.mark.parametrize("adj_vectors", [0, 1, 2, 3, 4])
+def test_fused_grad_hvp_vs_oracle(torch, small, B, adj_vectors):
+    """The benchmark's call shape, misfit + gradient + B products in one pass,
+    against the oracle.  B + 1 adjoint right-hand sides (the residual, then
+    the B Born data) are split into workgroups of `adj_vectors` (0: the
+    default rule, fours for an odd count of 5 or more), so B = 4, 6 and 16
+    cover full and ragged last groups of every size."""
+    g = small["g"]
+    m, vs, phi_o, grad_o, hv_o = _fused_reference(small, B)
+    say(f"entry: fwi_misfit_grad_hvp small B={B}, adj_vectors={adj_vectors}")
+    p = make_plan(g, options={"adj_vectors": adj_vectors})
+    phi, grad, hv = p.misfit_grad_hvp(dev(torch, m), dev(torch, small["dobs"]), dev(torch, vs))
+    hv = host(hv)
+    assert p.status() == 0
+    amp = np.linalg.norm(small["dobs"]) / np.sqrt(2 * phi_o)
+    assert amp < 20
+    assert float(phi) == pytest.approx(phi_o, rel=max(1e-5, 2 * TOL_DATA * amp))
+    eg = rel(host(grad), grad_o)
+    eh = [rel(hv[b], hv_o[b]) for b in range(B)]
+    say(f"  gradient {eg:.2e} (residual amplification {amp:.1f}); H v max {max(eh):.2e}")
+    assert eg < TOL_IMAGE
+    assert max(eh) < TOL_IMAGE
+
+
 def test_checkpoint_interval_invariance(torch):
     """Results do not depend on the checkpoint interval K: recomputed
     wavefields equal the stored ones bit for bit.  Even K runs two time steps
