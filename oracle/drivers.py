@@ -22,8 +22,11 @@ and the benchmark's CPU-baseline leg; shares no code with the HIP library.
   Step length by backtracking from t = 1 (halving) until the Armijo
   condition Phi(m + t p) <= Phi(m) + c1 t g^T p holds, c1 = 1e-4 (a trial
   whose Phi is not finite -- an unstable wave solve -- fails it); the pair
-  is stored only if s^T y > 0.  (The paper does not state its line search;
-  this is the reading.)
+  is stored only if s^T y > 0.  If no trial of the max_backtrack halvings
+  passes, no step is taken: the iterate, Phi and gradient stay, the step is
+  recorded as failed (t = 0) and the iteration stops, since the same
+  direction would be tried again.  (The paper does not state its line
+  search; this is the reading.)
 * gpCN (Section 2.3, eq. "gpcn"): m' = m_map + sqrt(1 - beta^2)(m_k - m_map)
   + beta zeta with zeta ~ N(0, Gamma~_post), accepted when u_k < min(1,
   exp(Delta(m_k) - Delta(m'))), Delta(m) = Phi(m) - 1/2 ||m - m_map||^2
@@ -79,7 +82,7 @@ def lbfgs(fg, m0, iters, h0=None, mem=5, c1=1e-4, max_backtrack=20):
     m = np.array(m0, dtype=np.float64)
     f, g = fg(m)
     S, Y = [], []
-    out = {"m": [m.copy()], "phi": [f], "t": [], "backtracks": [], "evals": 1}
+    out = {"m": [m.copy()], "phi": [f], "t": [], "backtracks": [], "evals": 1, "failed": False}
     for _ in range(iters):
         if h0 is None:
             gam = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])) if S else 1.0
@@ -93,10 +96,20 @@ def lbfgs(fg, m0, iters, h0=None, mem=5, c1=1e-4, max_backtrack=20):
             mn = m + t * p
             fn, gn = fg(mn)
             out["evals"] += 1
-            if (math.isfinite(fn) and fn <= f + c1 * t * gp) or nb == max_backtrack:
+            if math.isfinite(fn) and fn <= f + c1 * t * gp:
+                break
+            if nb == max_backtrack:
+                t = 0.0  # no acceptable step
                 break
             t *= 0.5
             nb += 1
+        if t == 0.0:
+            out["m"].append(m.copy())
+            out["phi"].append(f)
+            out["t"].append(0.0)
+            out["backtracks"].append(nb)
+            out["failed"] = True
+            break
         s, y = mn - m, gn - g
         if float(np.sum(s * y)) > 0.0:
             S.append(s)

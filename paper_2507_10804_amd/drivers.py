@@ -132,6 +132,7 @@ class Lbfgs:
         self.alpha = t.zeros(self.mem + 1, dtype=t.float64, device=dev)
         self.gamma = t.ones(1, dtype=t.float64, device=dev)
         self.slots = []  # oldest .. newest
+        self.failed = False  # a line search found no acceptable step
         self.history = {"phi": [self.f], "t": [], "backtracks": []}
 
     def direction(self):
@@ -158,8 +159,15 @@ class Lbfgs:
         while True:
             mn = v.lincomb(1.0, self.m, t, p)
             fn, gn = self.post.value_grad(mn)
-            if (math.isfinite(fn) and fn <= self.f + self.c1 * t * gp) or nb == self.max_backtrack:
+            if math.isfinite(fn) and fn <= self.f + self.c1 * t * gp:
                 break
+            if nb == self.max_backtrack:
+                # no acceptable step: the iterate, Phi and gradient stay
+                self.failed = True
+                self.history["phi"].append(self.f)
+                self.history["t"].append(0.0)
+                self.history["backtracks"].append(nb)
+                return {"phi": self.f, "t": 0.0, "backtracks": nb, "failed": True}
             t *= 0.5
             nb += 1
         slot = next(i for i in range(self.mem + 1) if i not in self.slots)
@@ -176,11 +184,14 @@ class Lbfgs:
         self.history["phi"].append(fn)
         self.history["t"].append(t)
         self.history["backtracks"].append(nb)
-        return {"phi": fn, "t": t, "backtracks": nb}
+        return {"phi": fn, "t": t, "backtracks": nb, "failed": False}
 
     def run(self, iters):
+        """Up to `iters` steps; stops after a failed line search (the same
+        direction would be tried again)."""
         for _ in range(iters):
-            self.step()
+            if self.step()["failed"]:
+                break
         return self.history
 
 

@@ -125,3 +125,27 @@ def test_lbfgs_backtracking_takes_the_largest_armijo_step(c1):
     out = Dr.lbfgs(fg, np.ones(1), 1, h0=lambda q: q, c1=c1)
     k = next(k for k in range(40) if 0.5 * a * (1 - a * 0.5 ** k) ** 2 <= 0.5 * a - c1 * 0.5 ** k * a * a)
     assert out["t"] == [0.5 ** k] and out["backtracks"] == [k]
+
+
+def test_lbfgs_failed_line_search_keeps_the_iterate():
+    """An objective that is finite only within 1e-9 of the start (every trial
+    step down to t = 2^-20 lands where the wave solve would be unstable):
+    no trial passes, so the iterate, Phi and the gradient stay, the step is
+    recorded as failed with t = 0, and the iteration stops instead of moving
+    to a point whose Phi is not finite."""
+    m0 = np.array([1.0, -2.0, 0.5])
+
+    def fg(m):
+        if np.linalg.norm(m - m0) > 1e-9:
+            return math.inf, np.full(3, np.nan)
+        return 0.5 * float(m @ m), m.copy()
+
+    out = Dr.lbfgs(fg, m0, 5, max_backtrack=20)
+    assert out["failed"]
+    assert out["t"] == [0.0] and out["backtracks"] == [20]
+    assert out["evals"] == 1 + 21
+    assert np.array_equal(out["m"][-1], m0) and out["phi"] == [out["phi"][0]] * 2
+    assert all(math.isfinite(f) for f in out["phi"])
+    # a finite objective in reach is unaffected: plain convergence on a quadratic
+    ok = Dr.lbfgs(lambda m: (0.5 * float(m @ m), m.copy()), m0, 3)
+    assert not ok["failed"] and ok["phi"][-1] < 1e-20
