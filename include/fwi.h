@@ -46,7 +46,11 @@
  * synchronously with a message retrievable by fwi_last_error() (thread
  * local).  Data-dependent conditions found on the device (m <= 0 or not
  * finite, Courant number above the stability limit, non-finite output) are
- * OR-ed into a status word read and cleared by fwi_status().
+ * recorded in the call's own status word, the first 4 bytes of its
+ * workspace (cleared when the call starts, read by fwi_workspace_status()),
+ * and OR-ed into the plan's status word (read and cleared by fwi_status()).
+ * Calls that run concurrently on separate workspaces therefore keep separate
+ * status words.
  */
 #ifndef FWI_MI355X_H
 #define FWI_MI355X_H
@@ -241,6 +245,12 @@ int fwi_profile_reset(fwi_plan *p);
 /* Synchronise `stream`, return the device status word in *status and clear
  * it. */
 int fwi_status(fwi_plan *p, void *stream, uint32_t *status);
+
+/* Synchronise `stream` and return in *status the status bits of the last
+ * compute call that used workspace `ws` (device pointer) -- the bits of that
+ * call alone, whatever other calls on the plan have flagged.  The word is
+ * left as it is (the next call on `ws` clears it). */
+int fwi_workspace_status(const fwi_plan *p, const void *ws, void *stream, uint32_t *status);
 
 const char *fwi_strerror(int code);
 const char *fwi_last_error(void);

@@ -34,6 +34,8 @@ hipError_t launch_fold(const Geo &g, const double *img, int G, int Bst, int b0, 
                        hipStream_t st);
 hipError_t launch_check_finite(const float *p, long long n, unsigned int *status,
                                hipStream_t st);
+hipError_t launch_status_open(unsigned int *status, hipStream_t st);
+hipError_t launch_status_merge(const unsigned int *from, unsigned int *into, hipStream_t st);
 }  // namespace fwi
 
 using namespace fwi;
@@ -151,6 +153,7 @@ Layout layout(const fwi_plan *p, int op, int B) {
     o = align_up(o + bytes);
     return at;
   };
+  take(sizeof(unsigned int));  // the call's status word, at offset 0
   L.c = take(F);
   L.s2m = take(F);
   if (needs_dc) L.dc = take(F * B);
@@ -191,6 +194,9 @@ T *at(void *ws, size_t off) {
     if (e_ != hipSuccess)                                                               \
       return fail(FWI_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_));         \
   } while (0)
+
+// Status word of the call that uses workspace `ws` (its first word).
+unsigned int *ws_status(void *ws) { return static_cast<unsigned int *>(ws); }
 
 int check_call(const fwi_plan *p, int op, int B, const void *ws, size_t ws_bytes) {
   if (!p) return fail(FWI_EINVAL, "plan is null");
@@ -386,7 +392,7 @@ int prologue(fwi_plan *p, const Layout &L, void *ws, const float *m, const float
              bool born, bool adj, hipStream_t st) {
   const Geo &g = p->geo;
   HIP_TRY(launch_setup(g, m, v, B, at<float>(ws, L.c), at<float>(ws, L.s2m),
-                       born ? at<float>(ws, L.dc) : nullptr, p->tabs.status, st));
+                       born ? at<float>(ws, L.dc) : nullptr, ws_status(ws), st));
   HIP_TRY(launch_fill(at<float>(ws, L.u), (long long)set_stride(g, 1), st));
   if (born) HIP_TRY(launch_fill(at<float>(ws, L.du), (long long)set_stride(g, B), st));
   if (adj) HIP_TRY(launch_fill(at<float>(ws, L.ckpt), (long long)g.fs * 2 * g.ns, st));
@@ -712,11 +718,13 @@ int fwi_forward(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_bytes
   if (!m || !d) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_FORWARD, 1);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, false, st)) return rc;
   HIP_TRY(launch_zero_t0(d, g.ns, g.nt, g.nr, st));
   if (int rc = forward_sweep(p, L, ws, 1, false, d, nullptr, false, st)) return rc;
-  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -726,11 +734,13 @@ int fwi_born(fwi_plan *p, const float *m, const float *v, int B, float *dd, void
   if (!m || !v || !dd) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_BORN, B);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   if (int rc = prologue(p, L, ws, m, v, B, true, false, st)) return rc;
   HIP_TRY(launch_zero_t0(dd, B * g.ns, g.nt, g.nr, st));
   if (int rc = forward_sweep(p, L, ws, B, true, nullptr, dd, false, st)) return rc;
-  HIP_TRY(launch_check_finite(dd, (long long)B * g.ns * g.nt * g.nr, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(dd, (long long)B * g.ns * g.nt * g.nr, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -740,12 +750,14 @@ int fwi_adjoint(fwi_plan *p, const float *m, const float *r, int B, float *gout,
   if (!m || !r || !gout) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_ADJOINT, B);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
   if (int rc = forward_sweep(p, L, ws, 1, false, nullptr, nullptr, true, st)) return rc;
   if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, 1.0, gout, st));
-  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -755,11 +767,13 @@ int fwi_forward_keep(fwi_plan *p, const float *m, float *d, void *ws, size_t ws_
   if (!m || !d) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_ADJOINT, 1);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
   HIP_TRY(launch_zero_t0(d, g.ns, g.nt, g.nr, st));
   if (int rc = forward_sweep(p, L, ws, 1, false, d, nullptr, true, st)) return rc;
-  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(d, (long long)g.ns * g.nt * g.nr, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -769,10 +783,12 @@ int fwi_adjoint_resume(fwi_plan *p, const float *r, int B, float *gout, void *ws
   if (!r || !gout) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_ADJOINT, B);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   if (int rc = reverse_sweep(p, L, ws, B, r, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, 1.0, gout, st));
-  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(gout, (long long)B * g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -782,6 +798,7 @@ int fwi_misfit(fwi_plan *p, const float *m, const float *dobs, double *phi, void
   if (!m || !dobs || !phi) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_MISFIT, 1);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   float *dres = at<float>(ws, L.dres);
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, false, st)) return rc;
@@ -789,6 +806,8 @@ int fwi_misfit(fwi_plan *p, const float *m, const float *dobs, double *phi, void
   if (int rc = forward_sweep(p, L, ws, 1, false, dres, nullptr, false, st)) return rc;
   HIP_TRY(launch_residual(dres, dobs, (long long)g.ns * g.nt * g.nr, at<double>(ws, L.part),
                           NPARTS, 0.5 * p->inv_noise_var, phi, st));
+  HIP_TRY(launch_check_finite(dres, (long long)g.ns * g.nt * g.nr, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -798,6 +817,7 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
   if (!m || !dobs || !phi || !gout) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_MISFIT_GRAD, 1);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   float *dres = at<float>(ws, L.dres);
   if (int rc = prologue(p, L, ws, m, nullptr, 0, false, true, st)) return rc;
@@ -807,7 +827,8 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
                           NPARTS, 0.5 * p->inv_noise_var, phi, st));
   if (int rc = reverse_sweep(p, L, ws, 1, dres, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, 1, 0, 1, p->inv_noise_var, gout, st));
-  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -817,6 +838,7 @@ int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, vo
   if (!m || !v || !hv) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_GN_HVP, B);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   float *dd = at<float>(ws, L.dd);
   if (int rc = prologue(p, L, ws, m, v, B, true, true, st)) return rc;
@@ -824,7 +846,8 @@ int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, vo
   if (int rc = forward_sweep(p, L, ws, B, true, nullptr, dd, true, st)) return rc;
   if (int rc = reverse_sweep(p, L, ws, B, dd, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B, 0, B, p->inv_noise_var, hv, st));
-  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -835,6 +858,7 @@ int fwi_misfit_grad_hvp(fwi_plan *p, const float *m, const float *dobs, const fl
   if (!m || !dobs || !v || !phi || !gout || !hv) return fail(FWI_EINVAL, "null array");
   hipStream_t st = static_cast<hipStream_t>(stream);
   const Layout L = layout(p, FWI_OP_GRAD_HVP, B);
+  HIP_TRY(launch_status_open(ws_status(ws), st));
   const Geo &g = p->geo;
   const long long nd = (long long)g.ns * g.nt * g.nr;
   float *dd = at<float>(ws, L.dd);  // [B+1][ns][nt][nr]: d - dobs, then J v_b
@@ -846,8 +870,9 @@ int fwi_misfit_grad_hvp(fwi_plan *p, const float *m, const float *dobs, const fl
   if (int rc = reverse_sweep(p, L, ws, B + 1, dd, st)) return rc;
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B + 1, 0, 1, p->inv_noise_var, gout, st));
   HIP_TRY(launch_fold(g, at<double>(ws, L.img), L.G, B + 1, 1, B, p->inv_noise_var, hv, st));
-  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, p->tabs.status, st));
-  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, p->tabs.status, st));
+  HIP_TRY(launch_check_finite(gout, (long long)g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_check_finite(hv, (long long)B * g.nz * g.nx, ws_status(ws), st));
+  HIP_TRY(launch_status_merge(ws_status(ws), p->tabs.status, st));
   return FWI_OK;
 }
 
@@ -886,6 +911,16 @@ int fwi_profile_read(fwi_plan *p, int kind, double *total_ms, int64_t *launches)
   }
   *total_ms = acc;
   *launches = (int64_t)p->marks[kind].size();
+  return FWI_OK;
+}
+
+int fwi_workspace_status(const fwi_plan *p, const void *ws, void *stream, uint32_t *status) {
+  if (!p || !ws || !status) return fail(FWI_EINVAL, "null argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  unsigned int v = 0;
+  HIP_TRY(hipStreamSynchronize(st));
+  HIP_TRY(hipMemcpy(&v, ws, sizeof(v), hipMemcpyDeviceToHost));
+  *status = v;
   return FWI_OK;
 }
 

@@ -948,6 +948,15 @@ __global__ void k_check_finite(const float *__restrict__ p, long long n, unsigne
   if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(status, 4u);
 }
 
+// A call's status word: cleared when the call starts; at its end its bits
+// are OR-ed into the plan's word as well.
+__global__ void k_status_open(unsigned int *status) { *status = 0u; }
+
+__global__ void k_status_merge(const unsigned int *__restrict__ from, unsigned int *into) {
+  const unsigned int v = *from;
+  if (v) atomicOr(into, v);
+}
+
 // ------------------------------------------------------------ host launchers
 
 static inline unsigned int blocks_for(long long n, int per) {
@@ -1035,6 +1044,16 @@ hipError_t launch_fold(const Geo &g, const double *img, int G, int Bst, int b0, 
   const long long n = (long long)g.nz * g.nx * B;
   hipLaunchKernelGGL(k_fold, dim3(blocks_for(n, 256)), dim3(256), 0, st, g, img, G, Bst, b0, B,
                      scale, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_open(unsigned int *status, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_open, dim3(1), dim3(1), 0, st, status);
+  return hipGetLastError();
+}
+
+hipError_t launch_status_merge(const unsigned int *from, unsigned int *into, hipStream_t st) {
+  hipLaunchKernelGGL(k_status_merge, dim3(1), dim3(1), 0, st, from, into);
   return hipGetLastError();
 }
 

@@ -38,7 +38,8 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_psfplus_workspace_size", "fwi_psfplus_build", "fwi_vec_workspace_size",
            "fwi_vec_dot", "fwi_vec_update", "fwi_lbfgs_pair", "fwi_lbfgs_loop1",
            "fwi_lbfgs_loop2", "fwi_plan_set_option", "fwi_plan_get_option",
-           "fwi_symbol_set_option", "fwi_symbol_get_option"]
+           "fwi_symbol_set_option", "fwi_symbol_get_option", "fwi_workspace_status",
+           "fwi_calib_copy"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 # plan options (include/fwi.h, FWI_OPT_*)
 OPTIONS = {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 2,
@@ -67,12 +68,15 @@ _lib = None
 _lib_lock = threading.Lock()
 
 
-def load_library(path: str = LIB_PATH):
-    """Load the in-tree HIP library (raises if it has not been built)."""
+def load_library(path: str | None = None):
+    """Load the in-tree HIP library (raises if it has not been built).  The
+    first call fixes the library for the process; `path` (else LIB_PATH)
+    names another build of it, such as the sanitizer build."""
     global _lib
     with _lib_lock:
         if _lib is not None:
             return _lib
+        path = path or LIB_PATH
         if not os.path.exists(path):
             raise FwiError(-4, f"{path} not built: run __graft_entry__.build()")
         lib = ctypes.CDLL(path)
@@ -139,6 +143,8 @@ def load_library(path: str = LIB_PATH):
             "fwi_plan_get_option": ([P, I, P], I),
             "fwi_symbol_set_option": ([P, I, I], I),
             "fwi_symbol_get_option": ([P, I, P], I),
+            "fwi_workspace_status": ([P, P, P, P], I),
+            "fwi_calib_copy": ([P, P, Z, I, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -403,6 +409,14 @@ class Plan:
         return {KERNEL_STEP: "k_step2<false>" if two else "k_step<false>",
                 KERNEL_STEP_BORN: "k_step2<true>" if two else "k_step<true>",
                 KERNEL_ADJOINT: "k_adjoint2" if two else "k_adjoint"}[kind]
+
+    def workspace_status(self, ws):
+        """Synchronise and return the status bits of the last call that used
+        workspace tensor `ws` (that call's alone)."""
+        st = ctypes.c_uint32()
+        _check(self.lib.fwi_workspace_status(self._h, self._p(ws), self._stream(),
+                                             ctypes.byref(st)))
+        return st.value
 
     def status(self):
         """Synchronise, return and clear the device status bits."""

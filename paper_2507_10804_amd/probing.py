@@ -11,7 +11,9 @@ replayed for every later batch.
 
 The library enqueues kernel launches only (no memset, no host copies), so the
 call is capture-safe; the workspace, model and batch buffers are allocated
-before capture and stay fixed.
+before capture and stay fixed.  The session owns its workspace (not the
+plan's cache), so the captured graph keeps pointing at live memory whatever
+the plan does with its own cached workspaces.
 """
 from __future__ import annotations
 
@@ -31,17 +33,18 @@ class ProbeSession:
         self.v = torch.zeros((self.batch, g.nz, g.nx), dtype=torch.float32, device=dev)
         self.hv = torch.empty((self.batch, g.nz, g.nx), dtype=torch.float32, device=dev)
         self.graph = None
-        plan.workspace(fwi.FWI_OP_GN_HVP, self.batch)  # allocate before capture
+        # allocated before capture and held for the session's lifetime
+        self.ws = plan.new_workspace(fwi.FWI_OP_GN_HVP, self.batch)
         if use_graph:
             side = torch.cuda.Stream(device=dev)
             side.wait_stream(torch.cuda.current_stream(dev))
             with torch.cuda.stream(side):  # eager run on a side stream first
-                plan.gn_hvp(self.m, self.v, out=self.hv)
+                plan.gn_hvp(self.m, self.v, out=self.hv, ws=self.ws)
             torch.cuda.current_stream(dev).wait_stream(side)
             torch.cuda.synchronize(dev)
             self.graph = torch.cuda.CUDAGraph()
             with torch.cuda.graph(self.graph):
-                plan.gn_hvp(self.m, self.v, out=self.hv)
+                plan.gn_hvp(self.m, self.v, out=self.hv, ws=self.ws)
             torch.cuda.synchronize(dev)
 
     def run(self, v: torch.Tensor) -> torch.Tensor:
@@ -56,5 +59,5 @@ class ProbeSession:
         if self.graph is not None:
             self.graph.replay()
         else:
-            self.plan.gn_hvp(self.m, self.v, out=self.hv)
+            self.plan.gn_hvp(self.m, self.v, out=self.hv, ws=self.ws)
         return self.hv[:n]

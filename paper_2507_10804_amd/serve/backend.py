@@ -5,6 +5,8 @@ slot, on datasets (plan, observed data, resident models) kept in HBM.  Every
 job allocates its own workspace on its slot's stream, so concurrent jobs never
 share scratch memory; its size -- forward checkpoints plus segment buffers
 plus batch fields -- is what the server reserves against the memory budget.
+A job's status bits live in its own workspace, so a flagged proposal fails
+its own request only (never a neighbour's running on another slot).
 """
 from __future__ import annotations
 
@@ -13,6 +15,7 @@ import threading
 import numpy as np
 
 from .. import fwi
+from .server import RequestError
 
 _OPS = {"misfit": fwi.FWI_OP_MISFIT, "forward": fwi.FWI_OP_FORWARD, "hvp": fwi.FWI_OP_GN_HVP}
 
@@ -22,6 +25,21 @@ class Dataset:
         self.plan = plan
         self.dobs = dobs
         self.models = models
+
+
+class FlaggedModel(RequestError):
+    """The library flagged the request's model or output (non-positive or
+    non-finite speed, Courant number above the stability limit, non-finite
+    result): the result would be meaningless and is not returned."""
+
+
+def _raise_flagged(plan, ws, what):
+    bits = plan.workspace_status(ws)
+    if bits:
+        names = [n for b, n in ((fwi.STATUS_BAD_MODEL, "model not positive and finite"),
+                                (fwi.STATUS_CFL, "Courant number above the stability limit"),
+                                (fwi.STATUS_NONFINITE, "non-finite output")) if bits & b]
+        raise FlaggedModel(f"{what}: " + ", ".join(names))
 
 
 class GpuBackend:
@@ -102,6 +120,7 @@ class GpuBackend:
                              device=self.device)
                 hv = plan.gn_hvp(m, V.contiguous(), ws=ws)
                 st.synchronize()
+                _raise_flagged(plan, ws, "Hessian-vector product")
                 out, k = [], 0
                 for r, v in zip(reqs, vs):
                     n = v.shape[0]
@@ -115,11 +134,13 @@ class GpuBackend:
                              device=self.device)
                 phi = plan.misfit(r0.m, ds.dobs, ws=ws)
                 st.synchronize()
+                _raise_flagged(plan, ws, "misfit")
                 return [float(phi)]
             if r0.kind == "forward":
                 ws = t.empty(plan.workspace_bytes(fwi.FWI_OP_FORWARD), dtype=t.uint8,
                              device=self.device)
                 d = plan.forward(r0.m, ws=ws)
                 st.synchronize()
+                _raise_flagged(plan, ws, "forward")
                 return [d]
             raise ValueError(f"unknown request kind {r0.kind!r}")

@@ -134,3 +134,25 @@ def test_probe_session_graph_replays(torch):
             assert rel(out, ref) < 1e-6
         _ = (dev(torch, batch) * 2).sum().item()  # unrelated eager work in between
     assert rel(host(sess.run(dev(torch, combs))), oracle.gn_hvp(g, m, combs)) < 1e-4
+
+
+def test_probe_session_survives_workspace_release(torch):
+    """A session keeps its own workspace: after the plan drops its cached
+    workspaces and the memory is handed to another tensor, replays still
+    give the same result and leave that tensor untouched."""
+    from paper_2507_10804_amd import fwi, probing
+    say("entry: ProbeSession replay after Plan.release_workspaces, tiny, B=2")
+    g, m = tiny(nt=120)
+    plan = fwi.Plan(g)
+    v = synth.smooth_random_batch(g.nz, g.nx, seeds=[11, 12], sigma=2.0)
+    sess = probing.ProbeSession(plan, dev(torch, m), batch=2, use_graph=True)
+    first = host(sess.run(dev(torch, v))).copy()
+    plan.workspace(fwi.FWI_OP_GN_HVP, 2)  # a cached workspace of the same size
+    nbytes = plan.workspace_bytes(fwi.FWI_OP_GN_HVP, 2)
+    plan.release_workspaces()
+    torch.cuda.synchronize()
+    sentinel = torch.full((nbytes // 4,), 7.25, dtype=torch.float32, device="cuda")
+    again = host(sess.run(dev(torch, v)))
+    torch.cuda.synchronize()
+    assert np.array_equal(first, again)
+    assert bool((sentinel == 7.25).all())

@@ -96,3 +96,39 @@ def test_same_alone_and_in_the_mix():
             mm = np.float32(m2 if r.model == "m0" else 1.02 * m2).astype(np.float64)
             ho = oracle.gn_hvp(g, mm, r.v.double().cpu().numpy())
             assert rel(b.double().cpu().numpy(), ho) < 1e-4
+
+
+def test_flagged_proposal_fails_alone():
+    """A proposal above the stability limit and one with a negative speed,
+    submitted among good proposals on three concurrent slots: only their
+    futures fail (each job reads its own status word), the good ones return
+    the misfit the oracle gives."""
+    import torch
+    from paper_2507_10804_amd.serve import Request, Server
+    from paper_2507_10804_amd.serve.backend import FlaggedModel, GpuBackend
+
+    say("case: serving misfits with two flagged proposals, 3 slots")
+    dev = torch.device("cuda:0")
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
+    g, m = tiny(nx=48, nz=40, nt=160)
+    dobs = oracle.forward(g, m)
+    be = GpuBackend(slots=3)
+    plan = be.add_dataset("t", g, dobs=dobs)
+    props = [synth.smoothed_start(m, 2.0) + 15.0 * synth.smooth_random(m.shape, seed=s, sigma=3.0)
+             for s in range(8)]
+    bad = {3: 2.0 * props[3], 6: props[6].copy()}  # 4000+ m/s: Courant number 0.7
+    bad[6][10, 10] = -5.0
+    props = [bad.get(i, p) for i, p in enumerate(props)]
+    with Server(be, slots=3) as srv:
+        futs = [srv.submit(Request("misfit", "t", m=f32(p))) for p in props]
+        for i, f in enumerate(futs):
+            if i in bad:
+                with pytest.raises(FlaggedModel):
+                    f.result(timeout=120)
+            else:
+                phi_o, _ = oracle.misfit_grad(g, np.float32(props[i]).astype(np.float64), dobs)
+                amp = np.linalg.norm(dobs) / np.sqrt(2 * phi_o)
+                assert f.result(timeout=120) == pytest.approx(phi_o, rel=max(1e-4, 4e-5 * amp))
+    # the plan's own word has collected both kinds of flag
+    st = plan.status()
+    assert st & 1 and st & 2
