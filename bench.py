@@ -82,6 +82,23 @@ def algorithmic_bytes(g, B, nseg, K, fused=True):
     return {0: fwd + 2 * rec, 1: born, 2: adj(1) + adj(B)}
 
 
+UPDATE_BYTES = 16  # read u^n, u^{n-1}, c, write u^{n+1}: FP32, per field update
+
+
+def field_updates(g, B, fused=True):
+    """Field updates (one grid point of one wavefield advanced one step) of
+    one step, per kernel kind, on the padded grid: the unit of the headline
+    16 bytes per update.  Fused: a recompute of the forward field (kind 0),
+    forward + B Born fields (kind 1) and B + 1 adjoint fields (kind 2) over
+    nt - 1 steps.  Separate calls: the gradient's forward, two recomputes,
+    the Hv call's forward + B Born, and 1 + B adjoint fields."""
+    Np = (g.nz + 2 * g.nb) * (g.nx + 2 * g.nb)
+    per = g.ns * Np * (g.nt - 1)
+    if fused:
+        return {0: per, 1: (1 + B) * per, 2: (B + 1) * per}
+    return {0: 3 * per, 1: (1 + B) * per, 2: (1 + B) * per}
+
+
 def read_traffic(kind_name):
     """HBM bytes per launch from committed rocprofv3 counter runs, or None if
     absent or taken on a different kernel source."""
@@ -97,8 +114,12 @@ def read_traffic(kind_name):
 
 def cpu_baseline(g, m, v, threads, nt_sample):
     """The FP64 oracle, as it stands, on `threads` shots of the full grid for
-    nt_sample steps, one Gauss-Newton product; scaled to Hv/s of the whole
-    workload (64 shots x 4000 steps) by the fraction of shot-steps done."""
+    nt_sample steps, one Gauss-Newton product at a fresh model (forward,
+    Born, adjoint: shots run in parallel, one per thread); scaled to Hv/s of
+    the whole 64-shot x 4000-step workload by the fraction of shot-steps
+    done.  The GPU line's value is B products per fused pass (one forward,
+    B Born and B + 1 adjoint solves), so per product the GPU runs about two
+    solves per shot against the oracle's three here."""
     import oracle
 
     oracle.build(force=False)
@@ -113,56 +134,159 @@ def cpu_baseline(g, m, v, threads, nt_sample):
     oracle.gn_hvp(g1, m, v, nthreads=1)
     dt1 = time.perf_counter() - t1
     frac1 = (g1.nt - 1) / (g.ns * (g.nt - 1))
+    cpu = host_cpu()
     return {"value": frac / dt, "unit": "Hv/s", "cores": threads, "kind": "oracle",
-            "sample": f"one GN Hv on {threads} of {g.ns} shots, full 921x301 grid, "
-                      f"{nt_sample} of {g.nt} steps, {dt:.1f} s wall; scaled by shot-steps",
+            "sample": f"one GN Hv at a fresh model on {threads} of {g.ns} shots (one per "
+                      f"thread), full 921x301 grid, {nt_sample} of {g.nt} steps, {dt:.1f} s "
+                      f"wall; scaled by shot-steps",
             "per_core_value": frac1 / dt1,
             "per_core_sample": f"one shot, {g1.nt} steps, 1 thread, {dt1:.1f} s wall; "
-                               f"scaled by shot-steps"}
+                               f"scaled by shot-steps",
+            "host": cpu}
 
 
-def calibrate_copy(nbytes=2 << 30, reps=5):
-    """A plain copy of known size: its FETCH_SIZE / WRITE_SIZE counters give
-    the scale from counter units to bytes, its time the attainable HBM rate."""
+def small_case_timings(threads):
+    """The 128x128 / 4-shot / 500-step problem: Phi + gradient and one Hv by
+    the FP64 oracle (shots in parallel on `threads` threads, and on one) and
+    by the GPU (median of 5 calls, HIP events on the call's stream)."""
+    import oracle
     import torch
+    from paper_2507_10804_amd import fwi, synth
 
-    n = nbytes // 4
-    src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    g, m_true, m_eval = synth.config_small()
+    v = synth.smooth_random((g.nz, g.nx), seed=1, sigma=5.0)
+    dobs = oracle.forward(g, m_true)
+    out = {"workload": "128x128, 4 shots, 32 receivers, Ricker 10 Hz, nt=500"}
+    for name, nth in (("oracle_threads", threads), ("oracle_1_thread", 1)):
+        t0 = time.perf_counter()
+        oracle.misfit_grad(g, m_eval, dobs, nthreads=nth)
+        t1 = time.perf_counter()
+        oracle.gn_hvp(g, m_eval, v, nthreads=nth)
+        t2 = time.perf_counter()
+        out[name] = {"threads": nth, "misfit_grad_s": t1 - t0, "gn_hvp_s": t2 - t1}
+    plan = fwi.Plan(g)
+    f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device="cuda:0")
+    md, dd, vd = f32(m_eval), f32(dobs), f32(v)
+    st = torch.cuda.current_stream()
+    for name, fn in (("misfit_grad", lambda: plan.misfit_grad(md, dd)),
+                     ("gn_hvp", lambda: plan.gn_hvp(md, vd))):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(5):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            fn()
+            e1.record(st)
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        out[f"gpu_{name}_ms"] = float(np.median(ts))
+    return out
+
+
+COPY_VARIANTS = {0: "plain, one pass", 1: "non-temporal, one pass",
+                 2: "plain x4, one pass", 3: "non-temporal x4, one pass",
+                 4: "plain, 2048 WGs", 5: "non-temporal, 2048 WGs",
+                 6: "plain x4, 2048 WGs", 7: "non-temporal x4, 2048 WGs",
+                 8: "plain, 8192 WGs", 9: "non-temporal, 8192 WGs",
+                 10: "plain x4, 8192 WGs", 11: "non-temporal x4, 8192 WGs"}
+
+
+def copy_rates(nbytes=2 << 30, reps=10, variants=tuple(COPY_VARIANTS)):
+    """GB/s (read + write) of the library's STREAM-style copy (fwi_calib_copy,
+    16-byte accesses) of `nbytes`, per launch variant, HIP-event timed on the
+    stream the copies are enqueued on."""
+    import ctypes
+
+    import torch
+    from paper_2507_10804_amd import fwi
+
+    lib = fwi.load_library()
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda:0")
     dst = torch.empty_like(src)
-    dst.copy_(src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        dst.copy_(src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+    out = {}
+    for var in variants:
+        call = lambda: fwi._check(lib.fwi_calib_copy(ctypes.c_void_p(dst.data_ptr()),
+                                                      ctypes.c_void_p(src.data_ptr()),
+                                                      nbytes, var, sp))
+        call()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            call()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[var] = 2 * nbytes / (ms * 1e-3) / 1e9
+    assert bool((dst == 1.0).all())
+    return out
+
+
+def calibrate_copy(variant=None, reps=10, nbytes=2 << 30):
+    """The copy of known size: with --copy-variant, one variant `reps` times
+    (for counter runs: each dispatch reads and writes `nbytes`); without, a
+    sweep of every variant.  One JSON line."""
+    if variant is not None:
+        r = copy_rates(nbytes, reps, (variant,))
+        print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
+                          "variant": variant, "form": COPY_VARIANTS[variant],
+                          "dispatches": reps + 1, "gbs": r[variant]}), flush=True)
+        return
+    r = copy_rates(nbytes, reps)
+    best = max(r, key=r.get)
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes,
-                      "avg_ms": ms, "gbs": 2 * nbytes / (ms * 1e-3) / 1e9}), flush=True)
+                      "gbs": {COPY_VARIANTS[k]: round(v, 1) for k, v in r.items()},
+                      "best": COPY_VARIANTS[best], "best_gbs": r[best],
+                      "best_frac_of_peak": r[best] / HBM_PEAK_GBS}), flush=True)
+
+
+def host_cpu():
+    """Cores the process may use, what the OS reports, and the CPU model."""
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = os.cpu_count() or 1
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": affinity, "model": model,
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
 
 
 def serve_bench(args):
-    """Serving row: the same seeded closed-loop trace of 32 chains (misfit
-    proposals, single Hessian-vector products and probe batches on three
-    grids with resident models) through the plain one-at-a-time path and
-    through the continuous-batching server; one JSON line."""
+    """Serving row: the same seeded closed-loop trace of 32 chains -- misfit
+    (gpCN proposal) and single Hessian-vector requests 1:1, each on a grid,
+    shot count and record length drawn independently, four resident models
+    per grid -- through the plain one-at-a-time path and through the
+    continuous-batching server; per-request JSONL logs and one JSON line."""
     import torch
     from paper_2507_10804_amd.serve import Server
     from paper_2507_10804_amd.serve.backend import GpuBackend
     from paper_2507_10804_amd.serve import workload as wl
 
     be = GpuBackend(slots=args.slots, max_batch=16)
+    t_setup = time.monotonic()
     banks = wl.load_datasets(be)
-    log(f"serving: datasets {list(be.datasets)} resident, budget {be.mem_budget() / 1e9:.0f} GB")
+    log(f"serving: {len(be.datasets)} datasets resident after {time.monotonic() - t_setup:.0f} s, "
+        f"budget {be.mem_budget() / 1e9:.0f} GB")
     out = {"metric": "serving: Hv/s and p50/p99 latency, plain path vs continuous batching",
            "unit": "Hv/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f32",
            "data": "synthetic",
-           "config": {"workload": "32 closed-loop chains, offered 50 req/s; grids 256x128 "
-                                  "(16 shots, 2000 steps), 512x192 (32, 3000), 921x301 "
-                                  "(64, 4000); misfit proposals, single Hv, 1 in 10 a "
-                                  "4-vector probe batch; 4 resident models per grid",
-                      "requests_per_chain": args.requests_per_chain, "slots": args.slots}}
+           "config": {"workload": "32 closed-loop chains, offered 50 req/s; per request "
+                                  "independently: grid 256x128, 512x192 or 921x301, shots "
+                                  "16/32/64, nt 2000/3000/4000, misfit (gpCN proposal) or "
+                                  "one GN Hv 1:1, one of 4 resident models per grid",
+                      "requests_per_chain": args.requests_per_chain, "slots": args.slots,
+                      "warmup_s": args.serve_warmup}}
+    os.makedirs(args.serve_log_dir, exist_ok=True)
     for name, slots, coalesce in (("plain", 1, False), ("serving", args.slots, True)):
         with Server(be, slots=slots, coalesce=coalesce, max_batch=16) as srv:
             t0 = time.monotonic()
@@ -171,8 +295,11 @@ def serve_bench(args):
                                               seed=args.seed, warmup_s=args.serve_warmup,
                                               log=log)
         torch.cuda.synchronize()
+        path = os.path.join(args.serve_log_dir, f"serve_requests_{name}.jsonl")
+        wl.write_log(recs, path, t0)
         res = wl.summarize(recs, tw, t1)
         res["wall_s"] = t1 - t0
+        res["log"] = path
         log(f"{name}: {json.dumps(res)}")
         out[name] = res
     out["value"] = out["serving"]["hv_per_s"]
@@ -751,6 +878,9 @@ def main():
     ap.add_argument("--cpu-nt", type=int, default=1000)
     ap.add_argument("--no-profile", action="store_true",
                     help="skip the per-launch HIP events (rocprofv3 runs)")
+    ap.add_argument("--copy-variant", type=int, default=None,
+                    help="with --calibrate-copy: time one copy variant only")
+    ap.add_argument("--copy-reps", type=int, default=10)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain device-to-device copy of 2 GiB (the "
                          "reference kernel for HBM counters and attainable bandwidth)")
@@ -761,6 +891,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
+    ap.add_argument("--serve-log-dir", default=os.path.join(ROOT, "gpurun_out"))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--separate", action="store_true",
                     help="time the step as fwi_misfit_grad + fwi_gn_hvp instead of the fused "
@@ -784,7 +915,7 @@ def main():
         autograd_bench(args)
         return
     if args.calibrate_copy:
-        calibrate_copy()
+        calibrate_copy(args.copy_variant, args.copy_reps)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
@@ -900,37 +1031,58 @@ def main():
 
     if not args.no_profile:
         nseg = (g.nt - 1 + plan.K - 1) // plan.K
-        alg = algorithmic_bytes(g, B, nseg, plan.K, fused=fused)
+        comp = algorithmic_bytes(g, B, nseg, plan.K, fused=fused)
+        upd = field_updates(g, B, fused=fused)
         kern = {}
         for kind in KERNEL_NAMES:
             name = plan.kernel_name(kind)
             ms, n = plan.profile_read(kind)
             n_step = n / args.steps
-            per_launch = alg[kind] / n_step if n_step else 0.0
+            avg_s = 1e-3 * ms / max(n, 1)
+            u_launch = upd[kind] / n_step if n_step else 0.0
+            c_launch = comp[kind] / n_step if n_step else 0.0
             kern[name] = {"kind": ["forward", "forward+Born", "adjoint"][kind],
                           "steps_per_launch": plan.kernel_steps(kind),
-                          "launches_per_step": n_step, "avg_us": 1e3 * ms / max(n, 1),
+                          "launches_per_step": n_step, "avg_us": 1e6 * avg_s,
                           "total_ms_per_step": ms / args.steps,
-                          "alg_bytes_per_launch": per_launch,
-                          "achieved_gbs": per_launch / (1e-3 * ms / max(n, 1)) / 1e9 if n else 0}
+                          "field_updates_per_launch": u_launch,
+                          "alg_bytes_per_launch": UPDATE_BYTES * u_launch,
+                          "achieved_gbs": UPDATE_BYTES * u_launch / avg_s / 1e9 if n else 0.0,
+                          "compulsory_bytes_per_launch": c_launch,
+                          "compulsory_gbs": c_launch / avg_s / 1e9 if n else 0.0}
         plan.profile(False)
         dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"])
         k = kern[dom]
         traffic = read_traffic(dom)
-        out["roofline"] = {"bound": "hbm", "kernel": dom, "achieved": k["achieved_gbs"],
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": k["achieved_gbs"] / HBM_PEAK_GBS,
-                           "traffic": traffic,
-                           "alg_bytes_per_launch": k["alg_bytes_per_launch"],
-                           "avg_launch_us": k["avg_us"]}
+        copy = copy_rates(reps=5)
+        attain = max(copy.values())
+        out["roofline"] = {
+            "bound": "hbm", "kernel": dom,
+            "achieved": k["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": k["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
+            "alg_bytes_per_launch": k["alg_bytes_per_launch"],
+            "unit_bytes_per_field_update": UPDATE_BYTES,
+            "avg_launch_us": k["avg_us"],
+            "counter_gbs": traffic / (1e-6 * k["avg_us"]) / 1e9 if traffic else None,
+            "counter_frac": traffic / (1e-6 * k["avg_us"]) / 1e9 / HBM_PEAK_GBS if traffic else None,
+            "compulsory_bytes_per_launch": k["compulsory_bytes_per_launch"],
+            "compulsory_gbs": k["compulsory_gbs"],
+            "compulsory_frac": k["compulsory_gbs"] / HBM_PEAK_GBS,
+            "attainable_copy_gbs": attain,
+            "attainable_copy_frac": attain / HBM_PEAK_GBS}
         out["kernels"] = kern
 
     if not args.no_cpu_baseline:
-        try:
-            threads = min(16, len(os.sched_getaffinity(0)))
-        except AttributeError:
-            threads = min(16, os.cpu_count() or 1)
+        # the process's CPU share: the cores it may run on, capped by the
+        # OpenMP thread count the host sets for it
+        cpu = host_cpu()
+        threads = cpu["affinity"]
+        if cpu["omp_num_threads"]:
+            threads = min(threads, int(cpu["omp_num_threads"]))
+        del hv, dobs
+        plan.release_workspaces()
         out["cpu_baseline"] = cpu_baseline(g, m_eval, vs[0], threads, args.cpu_nt)
+        out["cpu_baseline"]["small_case"] = small_case_timings(threads)
     print(json.dumps(out), flush=True)
 
 

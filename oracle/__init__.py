@@ -29,14 +29,35 @@ _LIB = os.path.join(_HERE, "_fwi_oracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc -O2 (IEEE FP64, no fast-math)."""
+SANITIZED_LIB = os.path.join(_HERE, "_build", "asan", "_fwi_oracle.so")
+CLANG = "/opt/rocm/llvm/bin/clang"
+
+
+def build(force: bool = True, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc -O2 (IEEE FP64, no fast-math).  With
+    `sanitize`, a checking build (clang, AddressSanitizer + UndefinedBehavior
+    Sanitizer, same arithmetic flags) goes to _build/asan/ instead."""
+    if sanitize:
+        os.makedirs(os.path.dirname(SANITIZED_LIB), exist_ok=True)
+        tmp = SANITIZED_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call([CLANG, "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+                               "-fno-fast-math", "-ffp-contract=off", "-fno-omit-frame-pointer",
+                               "-fsanitize=address,undefined", "-shared-libasan", _SRC, "-o",
+                               tmp, "-lm"])
+        os.replace(tmp, SANITIZED_LIB)
+        return SANITIZED_LIB
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                                "-fno-fast-math", "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
+
+
+def use_library(path: str) -> None:
+    """Load the oracle from `path` (e.g. the sanitizer build) instead."""
+    global _LIB, _lib
+    _LIB, _lib = path, None
 
 
 class _Geom(ctypes.Structure):

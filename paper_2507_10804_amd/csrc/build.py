@@ -16,7 +16,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfwi_mi355x.so")
 SOURCES = ["fwi_kernels.hip", "fwi_psf.hip", "fwi_lowrank.hip", "fwi_symbol.hip", "fwi_opt.hip",
-           "fwi_api.cpp"]
+           "fwi_calib.hip", "fwi_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",
@@ -24,26 +24,40 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
          "-Wall", "-Wno-unused-function", "-I", os.path.join(ROOT, "include")]
 
 
-def build(verbose: bool = False) -> str:
+# Host-side AddressSanitizer + UndefinedBehaviorSanitizer build of the plan
+# code (CPU checks only; the device code is built as usual).  Every sanitizer
+# flag applies to the host pass alone.
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-shared-libasan"]
+SANITIZED_LIB = os.path.join(HERE, "_build", "asan", "libfwi_mi355x.so")
+
+
+def build(verbose: bool = False, sanitize: bool = False) -> str:
+    """Compile every source and link the library; with `sanitize`, the host
+    plan code (fwi_api.cpp) carries ASan and UBSan and the library goes to
+    _build/asan/ (load it with libclang_rt.asan preloaded)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", "asan") if sanitize else os.path.join(HERE, "_build")
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
-        cmd = [HIPCC, *FLAGS, *lang, "-c", os.path.join(HERE, src), "-o", obj]
+        extra = SANITIZE + ["-g"] if sanitize and src.endswith(".cpp") else []
+        cmd = [HIPCC, *FLAGS, *extra, *lang, "-c", os.path.join(HERE, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
+    lib = SANITIZED_LIB if sanitize else LIB
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", *(SANITIZE if sanitize else []),
+           *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, sanitize="--sanitize" in sys.argv))

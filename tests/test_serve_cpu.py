@@ -222,3 +222,56 @@ def test_shutdown_cancels_pending():
     srv.shutdown()
     with pytest.raises(Cancelled):
         pending.result(timeout=5)
+
+
+class _Dataset:
+    def __init__(self, geom, models):
+        self.plan = type("P", (), {"geom": geom})()
+        self.models = models
+        self.dobs = None
+
+
+def test_serving_trace_draws_and_request_log(tmp_path):
+    """The serving trace draws grid, shot count and record length
+    independently and misfit / Hessian-vector requests 1:1, and the
+    per-request JSONL log has one complete line per request.  Runs the
+    closed loop against the simulated backend on CPU tensors."""
+    import json
+
+    from paper_2507_10804_amd import synth
+    from paper_2507_10804_amd.serve import workload as wl
+
+    be = FakeBackend(per_req=0.0005, per_vec=0.0, budget=10 ** 9)
+    be.device = torch.device("cpu")
+    be.datasets = {}
+    banks = {}
+    for grid, (nx, nz) in wl.GRIDS.items():
+        nx, nz = nx // 16, nz // 16  # small stand-ins: the draw only needs shapes
+        models = {f"m{j}": torch.full((nz, nx), 2000.0 + j) for j in range(len(wl.SMOOTHING))}
+        for ns in wl.SHOTS:
+            for nt in wl.NTS:
+                g = synth.make_geometry(nx, nz, nt=10, ns=2, rec_ix=[1], f0=8.0, v_nominal=5500.0)
+                be.datasets[wl.dataset_key(grid, ns, nt)] = _Dataset(g, models)
+        banks[grid] = torch.zeros((4, nz, nx))
+    with Server(be, slots=4) as srv:
+        recs, tw, t1 = wl.run_closed_loop(srv, be, banks, chains=8, rate=4000.0,
+                                          requests_per_chain=60, seed=3)
+    assert len(recs) == 480 and all(r["ok"] for r in recs)
+    kinds = [r["kind"] for r in recs]
+    assert abs(kinds.count("misfit") - kinds.count("hvp")) < 0.15 * len(recs)
+    for field, values in (("grid", wl.GRIDS), ("shots", wl.SHOTS), ("nt", wl.NTS)):
+        counts = [sum(r[field] == v for r in recs) for v in values]
+        assert min(counts) > 0.2 * len(recs), (field, counts)
+    # independence: every (grid, shots, nt) combination occurs
+    assert len({(r["grid"], r["shots"], r["nt"]) for r in recs}) == 27
+    path = tmp_path / "requests.jsonl"
+    wl.write_log(recs, str(path), tw)
+    lines = [json.loads(x) for x in path.read_text().splitlines()]
+    assert len(lines) == len(recs)
+    for x in lines:
+        assert {"grid", "shots", "nt", "kind", "queue_ms", "device_ms", "latency_ms",
+                "batch", "ok"} <= set(x)
+        assert x["latency_ms"] >= x["device_ms"] >= 0 and x["queue_ms"] >= 0
+    s = wl.summarize(recs, tw, t1)
+    assert s["requests"] == len(recs) and s["hv_per_s"] > 0 and s["misfit_per_s"] > 0
+    assert s["p99_ms"] >= s["p50_ms"]
