@@ -212,6 +212,22 @@ int fwi_misfit_grad(fwi_plan *p, const float *m, const float *dobs, double *phi,
 int fwi_gn_hvp(fwi_plan *p, const float *m, const float *v, int B, float *hv, void *ws,
                size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): fwi_gn_hvp
+ * with its workspace in a fixed array of FWI_NOALLOC_MAX_BYTES that the
+ * library holds on every GPU it runs on (until the process ends), instead of
+ * caller memory.  Same arguments, results and errors as fwi_gn_hvp, without
+ * ws; FWI_ENOMEM (with a message) when fwi_workspace_size(FWI_OP_GN_HVP, B)
+ * exceeds the array -- problems about the size of a 128 x 128 grid with 4
+ * shots and 500 steps fit up to B = 5.  Calls no allocating routine.  All
+ * calls on one GPU share that GPU's array: calls that overlap in time on one
+ * GPU (other streams, other threads, other plans) race and must not be
+ * issued.  The array keeps the last call's contents; every call clears what
+ * it needs. */
+#define FWI_NOALLOC_MAX_BYTES (64u << 20)
+int fwi_gn_hvp_noalloc(fwi_plan *p, const float *m, const float *v, int B, float *hv,
+                       void *stream);
+
 /* Misfit, gradient and B Gauss-Newton products at one model, in one pass
  * (Section 3: a Hessian product reuses the forward wavefield of the gradient
  * at the same model, leaving two solves per source and vector).  Outputs are

@@ -16,7 +16,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfwi_mi355x.so")
 SOURCES = ["fwi_kernels.hip", "fwi_psf.hip", "fwi_lowrank.hip", "fwi_symbol.hip", "fwi_opt.hip",
-           "fwi_calib.hip", "fwi_api.cpp"]
+           "fwi_calib.hip", "fwi_noalloc.hip", "fwi_api.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=off",

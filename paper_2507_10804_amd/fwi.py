@@ -39,7 +39,7 @@ EXPORTS = ["fwi_abi_version", "fwi_plan_create", "fwi_plan_destroy", "fwi_plan_d
            "fwi_vec_dot", "fwi_vec_update", "fwi_lbfgs_pair", "fwi_lbfgs_loop1",
            "fwi_lbfgs_loop2", "fwi_plan_set_option", "fwi_plan_get_option",
            "fwi_symbol_set_option", "fwi_symbol_get_option", "fwi_workspace_status",
-           "fwi_calib_copy"]
+           "fwi_calib_copy", "fwi_gn_hvp_noalloc"]
 KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 # plan options (include/fwi.h, FWI_OPT_*)
 OPTIONS = {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 2,
@@ -145,6 +145,7 @@ def load_library(path: str | None = None):
             "fwi_symbol_get_option": ([P, I, P], I),
             "fwi_workspace_status": ([P, P, P, P], I),
             "fwi_calib_copy": ([P, P, Z, I, P], I),
+            "fwi_gn_hvp_noalloc": ([P, P, P, I, P, P], I),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)

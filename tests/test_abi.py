@@ -241,3 +241,17 @@ def test_no_environment_knobs():
     for name in os.listdir(csrc):
         if name.endswith((".hip", ".cpp", ".h")):
             assert "getenv" not in open(os.path.join(csrc, name)).read(), name
+
+
+def test_noalloc_refuses_oversized_problem_on_host(lib):
+    """The allocation-free product checks the problem against its fixed array
+    before any device work: the 64-shot, 4000-step full grid is refused with
+    FWI_ENOMEM and a message (no GPU needed, the plan is not even bound)."""
+    geom, _, _ = synth.config_layered(nt=4000)
+    rc, h, _ = _plan(lib, geom)
+    assert rc == 0
+    fn = lib.fwi_gn_hvp_noalloc
+    assert fn(h, None, None, 1, None, None) == -3
+    assert b"fixed" in lib.fwi_last_error()
+    assert fn(h, None, None, 0, None, None) == -1  # batch out of range
+    lib.fwi_plan_destroy(h)
