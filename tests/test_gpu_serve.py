@@ -132,3 +132,53 @@ def test_flagged_proposal_fails_alone():
     # the plan's own word has collected both kinds of flag
     st = plan.status()
     assert st & 1 and st & 2
+
+
+def test_same_alone_and_in_the_mix_256x128():
+    """The serving trace's smallest grid at its real size (256 x 128, 16
+    shots, 2000 steps, layered-faulted model, four resident models): misfit
+    proposals and single Hessian-vector products of one closed-loop trace,
+    run through the plain path and through the continuous-batching server
+    with three slots; misfits are bitwise equal, products agree to 1e-6
+    (merged batches change only the shot grouping), and one product meets
+    the FP64 oracle."""
+    import torch
+    from paper_2507_10804_amd.serve import Server
+    from paper_2507_10804_amd.serve import workload as wl
+    from paper_2507_10804_amd.serve.backend import GpuBackend
+
+    say("case: serving trace on 256x128, 16 shots, nt=2000; plain vs 3 slots")
+    be = GpuBackend(slots=3)
+    banks = wl.load_datasets(be, grids=("g256",), shots=(16,), nts=(2000,))
+
+    def draw(rng):
+        return wl.draw_request(rng, be, banks, grids=("g256",), shots=(16,), nts=(2000,))
+
+    def trace():
+        rng = np.random.default_rng(5)
+        return [draw(rng) for _ in range(16)]
+
+    with Server(be, slots=1, coalesce=False) as srv:
+        alone = [srv.submit(r).result(timeout=300) for r, _ in trace()]
+    reqs = trace()
+    with Server(be, slots=3, coalesce=True, max_batch=8) as srv:
+        futs = [srv.submit(r) for r, _ in reqs]
+        mixed = [f.result(timeout=300) for f in futs]
+        batches = [f.request.batch for f in futs]
+    torch.cuda.synchronize()
+    say(f"  kinds {[d['kind'][0] for _, d in reqs]}, batch sizes {batches}")
+    assert {d["kind"] for _, d in reqs} == {"misfit", "hvp"}
+    for i, (a, b, (r, d)) in enumerate(zip(alone, mixed, reqs)):
+        if d["kind"] == "misfit":
+            assert a == b, f"request {i}: misfit differs in the mix"
+        else:
+            e = rel(b.double().cpu().numpy(), a.double().cpu().numpy())
+            assert e < 1e-6, f"request {i}: Hv differs in the mix ({e:.2e})"
+    i = next(i for i, (_, d) in enumerate(reqs) if d["kind"] == "hvp")
+    r, d = reqs[i]
+    ds = be.datasets[r.dataset]
+    m = ds.models[r.model].double().cpu().numpy()
+    ho = oracle.gn_hvp(ds.plan.geom, m, r.v.double().cpu().numpy())
+    e = rel(mixed[i].double().cpu().numpy(), ho)
+    say(f"  request {i}: rel-L2 Hv vs oracle {e:.2e}")
+    assert e < 1e-4
