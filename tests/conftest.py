@@ -18,6 +18,10 @@ def pytest_addoption(parser):
 def pytest_configure(config):
     lib = config.getoption("--fwi-lib")
     if lib:
+        try:  # torch's HIP runtime must be the one the library binds to
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         from paper_2507_10804_amd import fwi
         fwi.load_library(os.path.abspath(lib))
     olib = config.getoption("--oracle-lib")
