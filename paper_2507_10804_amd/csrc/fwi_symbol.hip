@@ -434,6 +434,19 @@ __device__ inline int xcd_band(int id, int nbands) {
   return band < nbands ? band : -1;
 }
 
+// Work item of a workgroup in a one-dimensional grid of units x `per`
+// items: consecutive workgroup ids go round-robin to the 8 XCDs, so ids are
+// remapped to give every XCD a contiguous run, in which the `per` items of
+// one unit are consecutive -- operands the items of a unit share come from
+// that XCD's L2 after the first read.
+__device__ inline void xcd_run(int per, int &unit, int &item) {
+  const int n = gridDim.x, id = blockIdx.x;
+  const int q = n / 8, rem = n % 8, x = id % 8, slot = id / 8;
+  const int lid = x < rem ? x * (q + 1) + slot : rem * (q + 1) + (x - rem) * q + slot;
+  unit = lid / per;
+  item = lid - unit * per;
+}
+
 // Forward row transforms of B real planes in[b][rows][cols] (cols <= mx, zero
 // beyond): out[b][rows][mx].  One row per workgroup.
 __global__ __launch_bounds__(NTH) void k_rows_fwd(SymGeo g, const float *__restrict__ in, int rows,
@@ -631,7 +644,10 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_w(SymGeo g, const float2
   for (int i = threadIdx.x; i < n; i += blockDim.x) tw[i] = g.fx.tw[i];
   __syncthreads();
   const int q = w / S, p = w - q * S;
-  const int row = blockIdx.x, v = blockIdx.y * (W / S) + q;
+  // the row's coefficient fields A are read by every vector group
+  int row, grp;
+  xcd_run(gridDim.x / nz, row, grp);
+  const int v = grp * (W / S) + q;
   const bool live = v < B;  // uniform over the wavefront
   float acc[NACC];
 #pragma unroll
@@ -785,7 +801,10 @@ __global__ __launch_bounds__(256) void k_rows_inv_blend_960(SymGeo g, const floa
   split960_tables<true>(g.fx, T2, T3);
   __syncthreads();
   const int q = w / S, p = w - q * S;
-  const int row = blockIdx.x, v = blockIdx.y * (W / S) + q;
+  // the row's coefficient fields A are read by every vector group
+  int row, grp;
+  xcd_run(gridDim.x / nz, row, grp);
+  const int v = grp * (W / S) + q;
   const bool live = v < B;  // uniform over the wavefront
   float acc[2][8];
 #pragma unroll
@@ -1323,7 +1342,7 @@ int blend_w(const fwi_symbol *s, const SymGeo &g, const float2 *z, int T, int nb
   const int S = s->split ? (W % s->split == 0 ? std::min(s->split, W) : 1)
                          : blend_split(W, g.nz, nb, T, 8192);
   const int vpw = W / S;
-  const dim3 grid(g.nz, (nb + vpw - 1) / vpw), block(64 * W);
+  const dim3 grid(g.nz * ((nb + vpw - 1) / vpw)), block(64 * W);
   const size_t lds = sizeof(float2) * (size_t)g.mx * (1 + W);
   if (g.mx == 960 && s->r960) {
     const size_t l960 = sizeof(float2) * (960 + 64 + (size_t)W * 15 * BL_P);
