@@ -153,7 +153,11 @@ enum {
   FWI_OPT_ADJ_ORDER = 7,        /* the same for the one-step adjoint                  */
   FWI_OPT_BLOCK_X = 8,          /* tiles per block of the blocked order, 1..64 (default 2); */
   FWI_OPT_BLOCK_Z = 9,          /*   set before fwi_plan_bind                               */
-  FWI_OPT_COUNT = 10
+  FWI_OPT_LDS_POISON = 10,      /* 0/1, debug (default 0): every stencil workgroup fills its
+                                   LDS with NaN before staging, so a read of an entry no
+                                   thread wrote (a missing halo value or barrier) makes the
+                                   outputs NaN (status bit FWI_STATUS_NONFINITE) */
+  FWI_OPT_COUNT = 11
 };
 
 /* Set option `option` to `value`.  FWI_EINVAL for an unknown option, a value

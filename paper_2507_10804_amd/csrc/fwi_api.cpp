@@ -70,7 +70,7 @@ struct fwi_plan {
          off_nloc = 0, off_ngidx = 0, off_nrp = 0, off_nrec = 0, off_order = 0;
   size_t off2[8] = {0, 0, 0, 0, 0, 0, 0, 0};  // two-step tables
   // requested options (fwi_plan_set_option), indexed by FWI_OPT_*
-  int opt[FWI_OPT_COUNT] = {0, 1, 1, 0, 0, 0, 0, 0, 2, 2};
+  int opt[FWI_OPT_COUNT] = {0, 1, 1, 0, 0, 0, 0, 0, 2, 2, 0};
   // advance two time steps per launch, per kernel family: the requested
   // option where K is even (the checkpoint levels must fall on launch
   // boundaries), else single steps
@@ -91,6 +91,7 @@ struct fwi_plan {
     step_order = opt[FWI_OPT_STEP_ORDER];
     born_order = opt[FWI_OPT_BORN_ORDER];
     adj_order = opt[FWI_OPT_ADJ_ORDER];
+    geo.poison = opt[FWI_OPT_LDS_POISON];
   }
   int adj_nb(int B) const {
     if (adj_pair > 0) return std::min(adj_pair, B);
@@ -428,7 +429,8 @@ int fwi_plan_set_option(fwi_plan *p, int option, int value) {
   switch (option) {
     case FWI_OPT_TWO_STEP_FORWARD:
     case FWI_OPT_TWO_STEP_BORN:
-    case FWI_OPT_TWO_STEP_ADJOINT: hi = 1; break;
+    case FWI_OPT_TWO_STEP_ADJOINT:
+    case FWI_OPT_LDS_POISON: hi = 1; break;
     case FWI_OPT_ADJ_VECTORS: hi = 4; break;
     case FWI_OPT_ADJ_SHOT_GROUP: hi = 65536; break;
     case FWI_OPT_STEP_ORDER:

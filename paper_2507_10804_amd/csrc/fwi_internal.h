@@ -58,6 +58,7 @@ struct Geo {
   int blk;       // tiles per block in the blocked workgroup order
   int nblocks;   // ceil(ntiles / blk)
   int tiles_x2, tiles_z2, ntiles2;  // two-step tiling
+  int poison;    // debug: fill LDS with NaN before use (FWI_OPT_LDS_POISON)
 };
 
 // Device block of a plan (offsets in int32 units from its base).

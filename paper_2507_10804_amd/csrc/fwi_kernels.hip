@@ -66,6 +66,14 @@ __device__ __forceinline__ void std_(double *base, unsigned e, double v) {
                                         0, 0);
 }
 
+// Debug mode (plan option FWI_OPT_LDS_POISON): fill a workgroup's LDS
+// arrays with NaN before anything is staged, so that a read of an entry no
+// thread wrote -- a missing halo value or a missing barrier -- turns the
+// outputs into NaN instead of silently reading a stale value.
+__device__ __forceinline__ void poison_lds(float *L, int n, int nthreads) {
+  for (int e = (int)threadIdx.x; e < n; e += nthreads) L[e] = __builtin_nanf("");
+}
+
 __device__ __forceinline__ float sponge_kappa(const Geo &g, int i, int j) {
   const int dxc = max(max(g.nb - j, 0), j - (g.nxp - 1 - g.nb));
   const int dzc = max(max(g.nb - i, 0), i - (g.nzp - 1 - g.nb));
@@ -196,6 +204,10 @@ __device__ __forceinline__ void gather_receivers(float *__restrict__ L, const fl
 template <bool BORN>
 __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs a) {
   __shared__ float L[LH * LW];
+  if (g.poison) {
+    poison_lds(L, LH * LW, NTHREADS);
+    __syncthreads();
+  }
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   // order 0: shot-major (neighbouring tiles of one shot are adjacent ids);
   // order 1: tile-major (the shots of one tile are adjacent ids, so operands
@@ -315,6 +327,10 @@ __global__ __launch_bounds__(NTHREADS) void k_step(Geo g, DevTables t, StepArgs 
 // added (times 2/m_pad) to the group's FP64 partial image.
 __global__ __launch_bounds__(NTHREADS) void k_adjoint(Geo g, DevTables t, AdjArgs a) {
   __shared__ float L[LH * LW];
+  if (g.poison) {
+    poison_lds(L, LH * LW, NTHREADS);
+    __syncthreads();
+  }
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   // order 0: field-major, tile fastest; order 1: tile-major with the vector
   // index fastest, so the forward wavefield w of a shot group (shared by all
@@ -530,6 +546,11 @@ template <bool BORN>
 __global__ __launch_bounds__(NTHREADS2) void k_step2(Geo g, DevTables t, Step2Args a) {
   __shared__ float LI[IZ * IX];
   __shared__ float LE[EZ * EX];
+  if (g.poison) {
+    poison_lds(LI, IZ * IX, NTHREADS2);
+    poison_lds(LE, EZ * EX, NTHREADS2);
+    __syncthreads();
+  }
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int s = lid / g.ntiles2, tile = lid - s * g.ntiles2;
   const int tzi = tile / g.tiles_x2, txi = tile - tzi * g.tiles_x2;
@@ -685,6 +706,12 @@ __global__ __launch_bounds__(NTHREADS2) __attribute__((amdgpu_waves_per_eu(4, 8)
   extern __shared__ float LIMG[];  // [nb][TZ2][EX]
   __shared__ float LI[IZ * IX];
   __shared__ float LE[EZ * EX];
+  if (g.poison) {
+    poison_lds(LI, IZ * IX, NTHREADS2);
+    poison_lds(LE, EZ * EX, NTHREADS2);
+    poison_lds(LIMG, a.nb * TZ2 * EX, NTHREADS2);
+    __syncthreads();
+  }
   const int lid = xcd_remap(blockIdx.x, gridDim.x);
   const int tile = lid % g.ntiles2;
   const int rest = lid / g.ntiles2;

@@ -44,7 +44,7 @@ KERNEL_STEP, KERNEL_STEP_BORN, KERNEL_ADJOINT = range(3)
 # plan options (include/fwi.h, FWI_OPT_*)
 OPTIONS = {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 2,
            "adj_vectors": 3, "adj_shot_group": 4, "step_order": 5, "born_order": 6,
-           "adj_order": 7, "block_x": 8, "block_z": 9}
+           "adj_order": 7, "block_x": 8, "block_z": 9, "lds_poison": 10}
 # symbol options (include/fwi_symbol.h, FWI_SYM_OPT_*)
 SYMBOL_OPTIONS = {"chunk_mb": 0, "blend_split": 1, "split_960": 2}
 

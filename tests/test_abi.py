@@ -208,10 +208,11 @@ def test_plan_options(lib):
         defaults[name] = v.value
     assert defaults == {"two_step_forward": 0, "two_step_born": 1, "two_step_adjoint": 1,
                         "adj_vectors": 0, "adj_shot_group": 0, "step_order": 0,
-                        "born_order": 0, "adj_order": 0, "block_x": 2, "block_z": 2}
+                        "born_order": 0, "adj_order": 0, "block_x": 2, "block_z": 2,
+                        "lds_poison": 0}
     for opt, bad in [(fwi.OPTIONS["two_step_born"], 2), (fwi.OPTIONS["adj_vectors"], 5),
                      (fwi.OPTIONS["step_order"], -1), (fwi.OPTIONS["block_x"], 0),
-                     (fwi.OPTIONS["block_z"], 65), (10, 0), (-1, 0)]:
+                     (fwi.OPTIONS["block_z"], 65), (fwi.OPTIONS["lds_poison"], 2), (11, 0), (-1, 0)]:
         assert lib.fwi_plan_set_option(h, opt, bad) == -1
     n_two, n_one = ctypes.c_size_t(), ctypes.c_size_t()
     assert lib.fwi_workspace_size(h, fwi.FWI_OP_GN_HVP, 4, ctypes.byref(n_two)) == 0

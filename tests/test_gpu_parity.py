@@ -366,3 +366,34 @@ def test_argument_errors(torch):
     rc = p.lib.fwi_forward(h, ctypes.c_void_p(ws.data_ptr()), ctypes.c_void_p(ws.data_ptr()),
                            ctypes.c_void_p(ws.data_ptr()), 16, None)
     assert rc == fwi.FWI_OP_FORWARD - 3  # FWI_ENOMEM
+
+
+def test_lds_poison_changes_nothing(torch):
+    """Debug mode FWI_OPT_LDS_POISON fills every stencil workgroup's LDS with
+    NaN before staging: if any kernel read an LDS entry that no thread of its
+    workgroup wrote (a missing halo value or barrier), the outputs would turn
+    NaN.  Every operation, in the one-step and the two-step forms, on a
+    ragged grid with receivers at tile edges, gives bitwise the same results
+    with and without it."""
+    g, m = tiny(nx=150, nz=50, nt=151, nb=10)
+    ix = np.array([53, 54, 54, 45, 46, 101, 102, 0, 149])
+    g.rec_zx = np.stack([np.array([1, 1, 1, 21, 22, 22, 20, 49, 0]), ix], 1).astype(np.int32)
+    dobs = oracle.forward(g, 1.03 * m)
+    vs = synth.smooth_random_batch(g.nz, g.nx, seeds=[61, 62, 63], sigma=2.0)
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=6)
+    mb, vb, rb, db = dev(torch, m), dev(torch, vs), dev(torch, r), dev(torch, dobs)
+    for flags in ("000", "111", "011"):
+        say(f"case: LDS poison on/off, kernel forms {flags}")
+        names = ("two_step_forward", "two_step_born", "two_step_adjoint")
+        opts = {n: int(f) for n, f in zip(names, flags)}
+        outs = []
+        for poison in (0, 1):
+            p = make_plan(g, options=dict(opts, lds_poison=poison))
+            res = [p.forward(mb), p.born(mb, vb), p.adjoint(mb, rb), p.gn_hvp(mb, vb)]
+            phi, grad, hv = p.misfit_grad_hvp(mb, db, vb)
+            res += [grad, hv, phi.reshape(1)]
+            outs.append([host(x) for x in res])
+            assert p.status() == 0
+        for a, b in zip(*outs):
+            assert np.all(np.isfinite(b))
+            assert np.array_equal(a, b)
