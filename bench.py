@@ -891,7 +891,7 @@ def main():
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--requests-per-chain", type=int, default=6)
     ap.add_argument("--serve-warmup", type=float, default=5.0)
-    ap.add_argument("--serve-log-dir", default=os.path.join(ROOT, "gpurun_out"))
+    ap.add_argument("--serve-log-dir", default=os.path.join(ROOT, "serve_logs"))
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--separate", action="store_true",
                     help="time the step as fwi_misfit_grad + fwi_gn_hvp instead of the fused "
