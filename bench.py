@@ -897,6 +897,11 @@ def main():
                     help="time the step as fwi_misfit_grad + fwi_gn_hvp instead of the fused "
                          "fwi_misfit_grad_hvp")
     args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
+              "with one all-reduce of the images, which is not implemented here; "
+              "use --gpus 1", file=sys.stderr)
+        sys.exit(2)
     if args.mode == "serve":
         serve_bench(args)
         return
@@ -917,11 +922,6 @@ def main():
     if args.calibrate_copy:
         calibrate_copy(args.copy_variant, args.copy_reps)
         return
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the Hessian-vector product shards over shots "
-              "with one all-reduce of the images, which is not implemented here; "
-              "use --gpus 1", file=sys.stderr)
-        sys.exit(2)
 
     import torch
     from paper_2507_10804_amd import fwi, synth

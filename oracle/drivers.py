@@ -17,8 +17,13 @@ and the benchmark's CPU-baseline leg; shares no code with the HIP library.
   applied between the loops.  H0 is one of
     - "identity": gamma_k I, gamma_k = s^T y / y^T y of the newest pair
       (Nocedal and Wright's eq. 7.20), 1 before the first pair;
-    - any linear operator, e.g. the prior R^-1 or (H~_d + R)^-1 of a Hessian
-      approximation (the paper's preconditioning), applied unscaled.
+    - any linear operator M, e.g. the prior R^-1 or (H~_d + R)^-1 of a
+      Hessian approximation (the paper's preconditioning), scaled the same
+      way: gamma_k M, gamma_k = s^T y / y^T M y of the newest pair, 1 before
+      the first pair (eq. 7.20 with M in place of the identity).  A truncated
+      approximation leaves the data Hessian out of most directions, where M
+      alone would take steps orders of magnitude too long; the scaling
+      brings the first trial step to the curvature seen along the last step.
   Step length by backtracking from t = 1 (halving) until the Armijo
   condition Phi(m + t p) <= Phi(m) + c1 t g^T p holds, c1 = 1e-4 (a trial
   whose Phi is not finite -- an unstable wave solve -- fails it); the pair
@@ -36,7 +41,9 @@ and the benchmark's CPU-baseline leg; shares no code with the HIP library.
 
 Pins (tests/test_oracle_drivers.py): the two-loop recursion equals the
 explicit BFGS inverse-Hessian update; L-BFGS with the exact inverse Hessian
-as H0 solves a quadratic in one unit step; with the scaled identity it
+as H0 solves a quadratic in one unit step, and with H0 a multiple c of it the
+second step is the unit step to the minimiser (gamma = 1/c); with the scaled
+identity it
 converges on a quadratic and decreases Phi monotonically; grad Phi against
 central differences on a small wave problem; gpCN accepts every proposal
 when the Laplace approximation is exact, and its proposal and acceptance
@@ -88,7 +95,8 @@ def lbfgs(fg, m0, iters, h0=None, mem=5, c1=1e-4, max_backtrack=20):
             gam = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])) if S else 1.0
             H0 = lambda q, gam=gam: gam * q
         else:
-            H0 = h0
+            gam = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * h0(Y[-1]))) if S else 1.0
+            H0 = lambda q, gam=gam: gam * h0(q)
         p = -two_loop(g, S, Y, H0)
         gp = float(np.sum(g * p))
         t, nb = 1.0, 0

@@ -5,8 +5,12 @@
   the wave-equation plan, the Matern prior R from :mod:`.lowrank`.
 * :class:`Lbfgs`: L-BFGS with the two-loop recursion of ``include/fwi_opt.h``
   and an initial inverse Hessian H0 that is either the scaled identity or any
-  operator -- the prior R^-1, or (H~_d + R)^-1 of a Hessian approximation
-  (the paper's preconditioning).  Backtracking from t = 1 by halving until
+  operator M -- the prior R^-1, or (H~_d + R)^-1 of a Hessian approximation
+  (the paper's preconditioning) -- scaled by gamma = s^T y / y^T M y of the
+  newest pair (Nocedal and Wright's eq. 7.20 with M for the identity; 1
+  before the first pair), so that a truncated approximation, which leaves
+  the data Hessian out of most directions, does not set trial steps orders
+  of magnitude too long.  Backtracking from t = 1 by halving until
   the Armijo condition Phi(m + t p) <= Phi(m) + c1 t g^T p holds (c1 =
   1e-4); a pair is stored only if s^T y > 0.
 * :func:`gpcn`: generalized preconditioned Crank-Nicolson MCMC (Section 2.3,
@@ -146,7 +150,12 @@ class Lbfgs:
             r = v.torch.empty_like(q)
             v.update(1.0, q, 0.0, r, ad=self.gamma)
         else:
+            gam = 1.0
+            if self.slots:
+                s, y = self.S[self.slots[-1]], self.Y[self.slots[-1]]
+                gam = v.dot(s, y) / v.dot(y, self.h0(y).contiguous())
             r = self.h0(q).contiguous()
+            v.update(gam, r, 0.0, r)
         fwi._check(lib.fwi_lbfgs_loop2(v.n, len(order), arr, _p(self.S), _p(self.Y), _p(self.rho),
                                        _p(self.alpha), _p(r), _p(v.ws), v.nws, v.st()))
         return v.update(-1.0, r, 0.0, r)

@@ -56,6 +56,40 @@ def test_lbfgs_exact_h0_solves_quadratic_in_one_step():
     assert np.allclose(out["m"][1], np.linalg.solve(A, b), rtol=1e-10)
 
 
+def test_lbfgs_scaled_operator_h0_recovers_the_unit_step():
+    """H0 = c A^-1 with c = 1000 on a quadratic: the first step (along the
+    Newton direction, c times too long) backtracks; its pair gives
+    gamma = s^T y / y^T H0 y = 1/c and the second direction is the Newton
+    step: unit step, no backtracking, onto the minimiser."""
+    n = 12
+    A = _spd(n, 5)
+    b = np.random.default_rng(6).standard_normal(n)
+    fg = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)
+    Ainv = np.linalg.inv(A)
+    out = Dr.lbfgs(fg, np.zeros(n), 2, h0=lambda q: 1000.0 * (Ainv @ q))
+    assert out["backtracks"][0] > 0
+    assert out["t"][1] == 1.0 and out["backtracks"][1] == 0
+    assert np.allclose(out["m"][2], np.linalg.solve(A, b), rtol=1e-9, atol=1e-12)
+
+
+def test_lbfgs_identity_operator_equals_scaled_identity():
+    """H0 given as the identity operator is scaled by s^T y / y^T y of the
+    newest pair, which is the built-in scaled identity (eq. 7.20): the two
+    runs take the same steps on a quadratic with condition number 50.  An
+    operator applied unscaled takes shorter accepted steps and fails."""
+    n = 20
+    rng = np.random.default_rng(7)
+    Q = np.linalg.qr(rng.standard_normal((n, n)))[0]
+    A = Q @ np.diag(np.geomspace(1.0, 50.0, n)) @ Q.T
+    b = rng.standard_normal(n)
+    fg = lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b)
+    ref = Dr.lbfgs(fg, np.zeros(n), 6)
+    op = Dr.lbfgs(fg, np.zeros(n), 6, h0=lambda q: q.copy())
+    assert op["t"] == ref["t"] and op["backtracks"] == ref["backtracks"]
+    for a, c in zip(op["m"], ref["m"]):
+        assert np.allclose(a, c, rtol=1e-12, atol=1e-14)
+
+
 def test_lbfgs_scaled_identity_converges_monotonically():
     n = 10
     A = _spd(n, 5, cond=20.0)
