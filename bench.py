@@ -741,7 +741,8 @@ def map_bench(args):
            "dtype": "f32 (FP64 reductions)", "data": "synthetic",
            "config": {"workload": f"layered-faulted 921x301, {g.ns} shots, nt={g.nt}; Matern "
                                   f"prior rho=500 m sigma=200 m/s at the smoothed model; L-BFGS "
-                                  f"mem 5, H0 = (H~_d + R)^-1 of a rank-{r} approximation, Armijo "
+                                  f"mem 5, H0 = gamma (H~_d + R)^-1 of a rank-{r} approximation (gamma = "
+                                  "s^T y / y^T H0 y of the newest pair), Armijo "
                                   f"backtracking; gpCN beta 0.2 with the same Laplace "
                                   f"approximation",
                       "iterations": args.steps},
