@@ -11,8 +11,10 @@ with a one-shot plan, and the 64-shot product is checked through the
 dot-product test, symmetry and additivity over shot subsets.
 
 Tolerances: 4000 FP32 leapfrog steps accumulate more rounding than the 500 of
-the small case; measured errors are printed and the bounds below are about
-4x above them.
+the small case; measured errors are printed.  The forward data meet the 1e-5
+target per output; the Hessian products are bounded at 1e-5 (2.5-4x above
+the measured values), the Born data at about 2x their measured error, and
+the images at the 1e-4 target.
 """
 import os
 import sys
@@ -54,7 +56,7 @@ def test_full_forward_sampled_shot(full):
     got = host(d[s, ::ts, ::rs])
     e = rel(got, gold["d"])
     say(f"  rel-L2 forward data (shot {s}) = {e:.3e}")
-    assert e < 4e-5
+    assert e < 1e-5
     assert full["plan"].status() == 0
 
 
@@ -87,13 +89,14 @@ def test_full_gn_hvp_sampled_shot(full):
     hv = host(plan1.gn_hvp(full["f32"](full["m_eval"]), full["f32"](v)))
     e = rel(hv, gold["hv"])
     say(f"  rel-L2 GN Hv (shot {s}) = {e:.3e}")
-    assert e < 1e-4
+    assert e < 1e-5
 
 
 def test_full_born_sampled_shot(full):
     """Born data at full size in the benchmark's batch of 16, every member a
     distinct multiple of the fixture's vector, sampled on one shot against
-    the oracle (target 1e-5 per output; the bound is the forward data's)."""
+    the oracle (target 1e-5 per output; bound about twice the measured
+    1.7e-5)."""
     say("entry: fwi_born 921x301, 64 shots, B=16 (sampled shot vs oracle)")
     g = full["g"]
     full["plan"].release_workspaces()
@@ -107,7 +110,7 @@ def test_full_born_sampled_shot(full):
     full["plan"].release_workspaces()
     e = [rel(got[b], (b + 1) / 16 * gold["dd"]) for b in range(16)]
     say(f"  rel-L2 Born data (shot {s}): member 0 {e[0]:.3e}, max over members {max(e):.3e}")
-    assert max(e) < 4e-5
+    assert max(e) < 3.5e-5
 
 
 def test_full_fused_grad_hvp_vs_oracle(full):
@@ -140,7 +143,7 @@ def test_full_fused_grad_hvp_vs_oracle(full):
     say(f"  Phi rel {ep:.2e}; gradient {eg:.3e} (residual amplification {amp:.1f}); "
         f"H v member 0 {eh[0]:.3e}, member 15 (the lone last group) {eh[15]:.3e}, "
         f"max {max(eh):.3e}")
-    assert max(eh) < 1e-4
+    assert max(eh) < 1e-5
     assert eg < max(1e-4, 3 * 1.3e-5 * amp)
     assert ep < max(1e-4, 2 * 1.3e-5 * amp)
 
@@ -169,7 +172,7 @@ def test_full_probe_batch_one_shot_vs_oracle(full):
     ec, er = rel(hv[0], gold["hv_comb"]), rel(hv[1], gold["hv_rad"])
     eh = rel(hv[63], 0.5 * gold["hv_comb"])
     say(f"  rel-L2 comb {ec:.3e}, smoothed Rademacher {er:.3e}, halved comb (slot 63) {eh:.3e}")
-    assert max(ec, er, eh) < 1e-4
+    assert max(ec, er, eh) < 1e-5
 
 
 def test_full_probe_batch_64_shots(full):
