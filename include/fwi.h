@@ -143,8 +143,8 @@ enum {
   FWI_OPT_TWO_STEP_BORN = 1,    /* 0/1: the same for forward + Born (default 1) */
   FWI_OPT_TWO_STEP_ADJOINT = 2, /* 0/1: the same for the adjoint (default 1) (*) */
   FWI_OPT_ADJ_VECTORS = 3,      /* right-hand sides per two-step adjoint workgroup,
-                                   1..4; 0 (default): pairs for even counts, fours for
-                                   odd counts of 5 or more */
+                                   1..4; 0 (default): pairs (the last group ragged for
+                                   odd counts), one group for 1 or 3 */
   FWI_OPT_ADJ_SHOT_GROUP = 4,   /* shots summed per adjoint workgroup; 0 (default):
                                    the largest power of two <= 16 that keeps >= 4096
                                    workgroups (*) */

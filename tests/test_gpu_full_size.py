@@ -115,11 +115,11 @@ def test_full_born_sampled_shot(full):
 
 def test_full_fused_grad_hvp_vs_oracle(full):
     """The benchmark's call, fwi_misfit_grad_hvp with B = 16, on the sampled
-    shot's plan: 17 adjoint right-hand sides in workgroups of four (the last
+    shot's plan: 17 adjoint right-hand sides in workgroups of two (the last
     one holding a single vector), in the benchmark's launch configuration.
     Members are distinct multiples (b+1)/16 of the fixture's vector; Phi, the
     gradient and all 16 products are compared with the oracle.  The observed
-    data come from the GPU forward map of the true model (FP32, 1.3e-5 from
+    data come from the GPU forward map of the true model (FP32, 4.5e-6 from
     the oracle's), whose error the residual amplifies by |dobs|/|d - dobs|."""
     say("entry: fwi_misfit_grad_hvp 921x301, one sampled shot, B=16 (vs oracle)")
     fwi, f32 = full["fwi"], full["f32"]

@@ -199,7 +199,7 @@ def test_fused_grad_hvp_vs_oracle(torch, small, B, adj_vectors):
     """The benchmark's call shape, misfit + gradient + B products in one pass,
     against the oracle.  B + 1 adjoint right-hand sides (the residual, then
     the B Born data) are split into workgroups of `adj_vectors` (0: the
-    default rule, fours for an odd count of 5 or more), so B = 4, 6 and 16
+    default rule, pairs with a ragged last group), so B = 4, 6 and 16
     cover full and ragged last groups of every size."""
     g = small["g"]
     m, vs, phi_o, grad_o, hv_o = _fused_reference(small, B)
