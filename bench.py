@@ -324,6 +324,31 @@ def _kernel_table(plan, steps, alg=None):
     return kern
 
 
+def hvp_field_updates(g, batches):
+    """Field updates of Gauss-Newton product calls with the given batch
+    sizes, per kernel kind: the forward recompute, the forward + B Born
+    fields, and B adjoint fields, each advanced nt - 1 steps."""
+    per = g.ns * (g.nz + 2 * g.nb) * (g.nx + 2 * g.nb) * (g.nt - 1)
+    return {0: per * len(batches), 1: per * sum(1 + b for b in batches),
+            2: per * sum(batches)}
+
+
+def _headline_unit(kern, plan, upd):
+    """Requote a kernel table built on compulsory bytes in the headline unit,
+    16 B per field update, keeping the compulsory figures beside it."""
+    for kind in KERNEL_NAMES:
+        kt = kern.get(plan.kernel_name(kind))
+        if not kt or "achieved_gbs" not in kt:
+            continue
+        u = upd[kind] / kt["launches_per_step"]
+        kt["compulsory_bytes_per_launch"] = kt.pop("alg_bytes_per_launch")
+        kt["compulsory_gbs"] = kt.pop("achieved_gbs")
+        kt["field_updates_per_launch"] = u
+        kt["alg_bytes_per_launch"] = UPDATE_BYTES * u
+        kt["achieved_gbs"] = UPDATE_BYTES * u / (kt["avg_us"] * 1e-6) / 1e9
+    return kern
+
+
 def probing_bench(args):
     """Batched probing row: 64 Gauss-Newton products per launch at the
     smoothed layered model (921x301, 64 shots, 4000 steps) on impulse combs
@@ -370,21 +395,8 @@ def probing_bench(args):
             if mode == "eager" and name == "rademacher":
                 nseg = (g.nt - 1 + plan.K - 1) // plan.K
                 alg = algorithmic_bytes_hvp(g, B, nseg)
-                out["kernels"] = _kernel_table(plan, 1, alg)
-                # the headline unit, 16 B per field update: forward + B Born
-                # fields and B adjoint fields advanced nt - 1 steps
-                Np = (g.nz + 2 * g.nb) * (g.nx + 2 * g.nb)
-                per = g.ns * Np * (g.nt - 1)
-                upd = {0: per, 1: (1 + B) * per, 2: B * per}
-                for kind in KERNEL_NAMES:
-                    kt = out["kernels"].get(plan.kernel_name(kind))
-                    if kt:
-                        u = upd[kind] / kt["launches_per_step"]
-                        kt["compulsory_bytes_per_launch"] = kt.pop("alg_bytes_per_launch")
-                        kt["compulsory_gbs"] = kt.pop("achieved_gbs")
-                        kt["field_updates_per_launch"] = u
-                        kt["alg_bytes_per_launch"] = UPDATE_BYTES * u
-                        kt["achieved_gbs"] = UPDATE_BYTES * u / (kt["avg_us"] * 1e-6) / 1e9
+                out["kernels"] = _headline_unit(_kernel_table(plan, 1, alg), plan,
+                                                hvp_field_updates(g, [B]))
             plan.profile(False)
         out[mode] = {"s_per_launch": float(np.mean(times)), "hv_per_s": B / float(np.mean(times))}
     out["value"] = out["graph"]["hv_per_s"]
@@ -528,7 +540,8 @@ def lowrank_bench(args):
     t_build = time.perf_counter() - t0
     nseg = (g.nt - 1 + plan.K - 1) // plan.K
     a1, a2 = algorithmic_bytes_hvp(g, k, nseg), algorithmic_bytes_hvp(g, lr.kept, nseg)
-    kern = _kernel_table(plan, 1, {kind: a1[kind] + a2[kind] for kind in a1})
+    kern = _headline_unit(_kernel_table(plan, 1, {kind: a1[kind] + a2[kind] for kind in a1}),
+                          plan, hvp_field_updates(g, [k, lr.kept]))
     plan.profile(False)
     plan.release_workspaces()
     del omega
@@ -810,10 +823,15 @@ def algorithmic_bytes_grad(g, nseg):
 def _roofline_from(kern, dom, note):
     k = kern[dom]
     ach = k.get("achieved_gbs")
-    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": None if ach is None else ach / HBM_PEAK_GBS, "traffic": None,
-            "alg_bytes_per_launch": k.get("alg_bytes_per_launch"), "avg_launch_us": k["avg_us"],
-            "note": note}
+    out = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": None if ach is None else ach / HBM_PEAK_GBS, "traffic": None,
+           "alg_bytes_per_launch": k.get("alg_bytes_per_launch"), "avg_launch_us": k["avg_us"],
+           "note": note}
+    if "compulsory_gbs" in k:
+        out["unit_bytes_per_field_update"] = UPDATE_BYTES
+        out["compulsory_gbs"] = k["compulsory_gbs"]
+        out["compulsory_frac"] = k["compulsory_gbs"] / HBM_PEAK_GBS
+    return out
 
 
 def algorithmic_bytes_hvp(g, B, nseg):
