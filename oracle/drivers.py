@@ -95,7 +95,11 @@ def lbfgs(fg, m0, iters, h0=None, mem=5, c1=1e-4, max_backtrack=20):
             gam = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * Y[-1])) if S else 1.0
             H0 = lambda q, gam=gam: gam * q
         else:
-            gam = float(np.sum(S[-1] * Y[-1]) / np.sum(Y[-1] * h0(Y[-1]))) if S else 1.0
+            gam = 1.0
+            if S:
+                yhy = float(np.sum(Y[-1] * h0(Y[-1])))
+                if yhy > 0.0 and math.isfinite(yhy):  # H0 positive definite: always
+                    gam = float(np.sum(S[-1] * Y[-1])) / yhy
             H0 = lambda q, gam=gam: gam * h0(q)
         p = -two_loop(g, S, Y, H0)
         gp = float(np.sum(g * p))

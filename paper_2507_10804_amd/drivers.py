@@ -153,7 +153,9 @@ class Lbfgs:
             gam = 1.0
             if self.slots:
                 s, y = self.S[self.slots[-1]], self.Y[self.slots[-1]]
-                gam = v.dot(s, y) / v.dot(y, self.h0(y).contiguous())
+                yhy = v.dot(y, self.h0(y).contiguous())
+                if yhy > 0.0 and math.isfinite(yhy):  # H0 positive definite: always
+                    gam = v.dot(s, y) / yhy
             r = self.h0(q).contiguous()
             v.update(gam, r, 0.0, r)
         fwi._check(lib.fwi_lbfgs_loop2(v.n, len(order), arr, _p(self.S), _p(self.Y), _p(self.rho),
