@@ -123,6 +123,7 @@ def cpu_baseline(g, m, v, threads, nt_sample):
     import oracle
 
     oracle.build(force=False)
+    threads = max(1, min(threads, g.ns))  # one shot per thread
     gs = g.with_shots(np.arange(threads)).with_nt(nt_sample)
     t0 = time.perf_counter()
     oracle.gn_hvp(gs, m, v, nthreads=threads)
@@ -1089,7 +1090,10 @@ def main():
         plan.profile(False)
         dom = max(kern, key=lambda k: kern[k]["total_ms_per_step"])
         k = kern[dom]
-        traffic = read_traffic(dom)
+        # the committed counter runs are of the default workload's launches
+        # (921x301, 64 shots, B = 16, one fused pass); other shapes get none
+        same = (g.nz, g.nx, g.ns, B, fused) == (301, 921, 64, 16, True)
+        traffic = read_traffic(dom) if same else None
         copy = copy_rates(reps=5)
         attain = max(copy.values())
         out["roofline"] = {

@@ -256,3 +256,16 @@ def test_noalloc_refuses_oversized_problem_on_host(lib):
     assert b"fixed" in lib.fwi_last_error()
     assert fn(h, None, None, 0, None, None) == -1  # batch out of range
     lib.fwi_plan_destroy(h)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a
+    message, before touching any device."""
+    import subprocess
+    import sys
+
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 2 and "one GPU" in r.stderr
+
