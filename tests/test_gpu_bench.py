@@ -13,10 +13,12 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def test_bench_line_fields():
-    print("case: bench.py on 921x301, 4 shots, nt=100, B=2, one step", flush=True)
+@pytest.mark.parametrize("extra", [[], ["--separate"]], ids=["fused", "separate"])
+def test_bench_line_fields(extra):
+    print(f"case: bench.py {' '.join(extra)} on 921x301, 4 shots, nt=100, B=2, one step",
+          flush=True)
     cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--shots", "4", "--nt", "100",
-           "--batch", "2", "--steps", "1", "--warmup", "0", "--cpu-nt", "20"]
+           "--batch", "2", "--steps", "1", "--warmup", "0", "--cpu-nt", "20", *extra]
     r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=600)
     assert r.returncode == 0, r.stderr[-3000:]
     lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
