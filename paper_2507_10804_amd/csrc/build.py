@@ -30,6 +30,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-ffp-contract=
 SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-shared-libasan"]
 SANITIZED_LIB = os.path.join(HERE, "_build", "asan", "libfwi_mi355x.so")
+EXAMPLE = os.path.join(PKG, "fwi_example")
 
 
 def build(verbose: bool = False, sanitize: bool = False) -> str:
@@ -56,7 +57,27 @@ def build(verbose: bool = False, sanitize: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, lib)
+    if not sanitize:
+        build_example(verbose)
     return lib
+
+
+def build_example(verbose: bool = False) -> str:
+    """Compile fwi_example.cpp, a host program (no device code) that calls the
+    library through include/fwi.h and the HIP runtime API alone, and link it
+    against the in-tree library (found next to the executable at run time)."""
+    tmp = EXAMPLE + ".tmp%d" % os.getpid()
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    cmd = [os.environ.get("CXX", "g++"), "-O2", "-std=c++17", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(rocm, "include"),
+           os.path.join(HERE, "fwi_example.cpp"), "-L", PKG, "-lfwi_mi355x",
+           "-L", os.path.join(rocm, "lib"), "-lamdhip64", "-Wl,-rpath,$ORIGIN",
+           "-Wl,-rpath," + os.path.join(rocm, "lib"), "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, EXAMPLE)
+    return EXAMPLE
 
 
 if __name__ == "__main__":

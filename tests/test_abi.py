@@ -269,3 +269,15 @@ def test_bench_refuses_more_than_one_gpu():
                        capture_output=True, text=True, timeout=300)
     assert r.returncode == 2 and "one GPU" in r.stderr
 
+
+
+def test_c_example_is_built_and_links():
+    """build() also compiles fwi_example, a caller of the C ABI that uses the
+    header and the HIP runtime alone; without arguments it loads both libraries,
+    prints its usage and exits with status 1 (no GPU call is made)."""
+    import subprocess
+
+    from paper_2507_10804_amd.csrc import build as hip_build
+
+    r = subprocess.run([hip_build.EXAMPLE], capture_output=True, text=True, timeout=60)
+    assert r.returncode == 1 and "usage:" in r.stderr
