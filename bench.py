@@ -46,10 +46,12 @@ def kernel_source_hash():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def algorithmic_bytes(g, B, nseg, K, fused=True):
+def algorithmic_bytes(g, B, nseg, K, fused=True, hist=False):
     """Compulsory HBM bytes of one step (misfit, gradient and B products at
     one model: one fused pass, or a gradient call plus a B-vector Hv call),
     per kernel kind: every array element a launch must read or write, once.
+    With `hist` (history mode, ckpt_every = 0) the forward sweeps store w^n
+    at every step instead of checkpoints, and nothing is recomputed.
 
     Np = padded grid points.  Per launch:
       forward step      4 Np (3 ns + 1)       u^n, u^{n-1}, c -> u^{n+1}
@@ -65,14 +67,20 @@ def algorithmic_bytes(g, B, nseg, K, fused=True):
     nzp, nxp = g.nz + 2 * g.nb, g.nx + 2 * g.nb
     Np = nzp * nxp
     ns, nr, nt = g.ns, g.nr, g.nt
-    ck_steps = nseg - 1
+    ck_steps = 0 if hist else nseg - 1
+
+    def adj(b):
+        return nt * (12 * Np * b * ns + 4 * b * ns * nr) + (nt - 1) * (4 * Np * ns + 8 * Np + 16 * Np * b)
+
+    keep = (nt - 1) * 4 * ns * Np if hist else 0  # w^n stores of the forward sweep
     fwd = (nt - 1) * (4 * Np * (3 * ns + 1) + 4 * ns * nr) + ck_steps * 8 * ns * Np
     rec = (nt - 1) * (4 * Np * (3 * ns + 1) + 4 * ns * Np)
     born = ((nt - 1) * (4 * Np * (3 * ns + 1) + 4 * Np * B * (3 * ns + 1) + 4 * B * ns * nr)
             + ck_steps * 8 * ns * Np)
-
-    def adj(b):
-        return nt * (12 * Np * b * ns + 4 * b * ns * nr) + (nt - 1) * (4 * Np * ns + 8 * Np + 16 * Np * b)
+    if hist:
+        if fused:
+            return {0: 0, 1: born + keep + (nt - 1) * 4 * ns * nr, 2: adj(B + 1)}
+        return {0: fwd + keep, 1: born + keep, 2: adj(1) + adj(B)}
 
     if fused:
         # one pass: forward+Born (gathering d and J v) + one recompute + adjoint(B + 1)
@@ -85,18 +93,19 @@ def algorithmic_bytes(g, B, nseg, K, fused=True):
 UPDATE_BYTES = 16  # read u^n, u^{n-1}, c, write u^{n+1}: FP32, per field update
 
 
-def field_updates(g, B, fused=True):
+def field_updates(g, B, fused=True, hist=False):
     """Field updates (one grid point of one wavefield advanced one step) of
     one step, per kernel kind, on the padded grid: the unit of the headline
     16 bytes per update.  Fused: a recompute of the forward field (kind 0),
     forward + B Born fields (kind 1) and B + 1 adjoint fields (kind 2) over
     nt - 1 steps.  Separate calls: the gradient's forward, two recomputes,
-    the Hv call's forward + B Born, and 1 + B adjoint fields."""
+    the Hv call's forward + B Born, and 1 + B adjoint fields.  History mode
+    (`hist`) has no recomputes."""
     Np = (g.nz + 2 * g.nb) * (g.nx + 2 * g.nb)
     per = g.ns * Np * (g.nt - 1)
     if fused:
-        return {0: per, 1: (1 + B) * per, 2: (B + 1) * per}
-    return {0: 3 * per, 1: (1 + B) * per, 2: (1 + B) * per}
+        return {0: 0 if hist else per, 1: (1 + B) * per, 2: (B + 1) * per}
+    return {0: (1 if hist else 3) * per, 1: (1 + B) * per, 2: (1 + B) * per}
 
 
 def read_traffic(kind_name):
@@ -930,6 +939,9 @@ def main():
     ap.add_argument("--serve-warmup", type=float, default=5.0)
     ap.add_argument("--serve-log-dir", default=os.path.join(ROOT, "serve_logs"))
     ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ckpt-every", type=int, default=50,
+                    help="checkpoint interval K of the default mode; 0 keeps the whole forward "
+                         "history instead (needs (nt - 1) x shots fields of workspace)")
     ap.add_argument("--separate", action="store_true",
                     help="time the step as fwi_misfit_grad + fwi_gn_hvp instead of the fused "
                          "fwi_misfit_grad_hvp")
@@ -963,7 +975,9 @@ def main():
     import torch
     from paper_2507_10804_amd import fwi, synth
 
-    g, m_true, m_eval = synth.config_layered(ns=args.shots, nt=args.nt)
+    g, m_true, m_eval = synth.config_layered(ns=args.shots, nt=args.nt,
+                                             ckpt_every=args.ckpt_every)
+    hist = args.ckpt_every == 0
     B = args.batch
     vs = synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, B + 1))
     dev = torch.device("cuda:0")
@@ -972,7 +986,7 @@ def main():
     f32 = lambda a: torch.as_tensor(np.asarray(a, np.float32), device=dev)
     mt, me, vd = f32(m_true), f32(m_eval), f32(vs)
     log(f"workload: 921x301 padded {plan.nzp}x{plan.nxp}, {g.ns} shots, {g.nr} receivers, "
-        f"nt={g.nt}, K={plan.K}, B={B}")
+        f"nt={g.nt}, K={'history' if hist else plan.K}, B={B}")
     dobs = plan.forward(mt)  # synthetic observed data (untimed)
     hv = torch.empty((B, g.nz, g.nx), dtype=torch.float32, device=dev)
     torch.cuda.synchronize()
@@ -1047,13 +1061,15 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"layered-faulted 921x301 dx=10m, {g.ns} shots, {g.nr} receivers, "
-                               f"Ricker 8 Hz, nt={g.nt}, K={plan.K}: misfit, gradient and "
+                               f"Ricker 8 Hz, nt={g.nt}, "
+                               f"{'whole forward history kept' if hist else f'K={plan.K}'}: "
+                               f"misfit, gradient and "
                                f"{B} GN Hv at one model per step"
                                + (", one fused pass (shared forward solve and recompute)"
                                   if fused else ", as two calls"),
                    "call": "fwi_misfit_grad_hvp" if fused else "fwi_misfit_grad + fwi_gn_hvp",
                    "grid": [g.nz, g.nx], "padded": [nzp, nxp], "shots": g.ns,
-                   "receivers": g.nr, "nt": g.nt, "batch": B, "ckpt_every": plan.K,
+                   "receivers": g.nr, "nt": g.nt, "batch": B, "ckpt_every": 0 if hist else plan.K,
                    "workspace_gb": round(ws_gb, 2)},
         "gpt_updates_per_s": gpts,
         "hbm_headline_frac": gpts * 1e9 * 16 / (HBM_PEAK_GBS * 1e9),
@@ -1068,8 +1084,8 @@ def main():
 
     if not args.no_profile:
         nseg = (g.nt - 1 + plan.K - 1) // plan.K
-        comp = algorithmic_bytes(g, B, nseg, plan.K, fused=fused)
-        upd = field_updates(g, B, fused=fused)
+        comp = algorithmic_bytes(g, B, nseg, plan.K, fused=fused, hist=hist)
+        upd = field_updates(g, B, fused=fused, hist=hist)
         kern = {}
         for kind in KERNEL_NAMES:
             name = plan.kernel_name(kind)
@@ -1092,7 +1108,7 @@ def main():
         k = kern[dom]
         # the committed counter runs are of the default workload's launches
         # (921x301, 64 shots, B = 16, one fused pass); other shapes get none
-        same = (g.nz, g.nx, g.ns, B, fused) == (301, 921, 64, 16, True)
+        same = (g.nz, g.nx, g.ns, B, fused, hist) == (301, 921, 64, 16, True, False)
         traffic = read_traffic(dom) if same else None
         copy = copy_rates(reps=5)
         attain = max(copy.values())

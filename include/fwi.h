@@ -108,7 +108,14 @@ typedef struct {
   int32_t nr;              /* receivers, shared by all shots */
   const int32_t *rec_zx;   /* nr x (iz, ix) model cells */
   const float *wavelet;    /* nt samples s(n dt) */
-  int32_t ckpt_every;      /* K: forward checkpoint interval in steps (>= 1) */
+  int32_t ckpt_every;      /* K: forward checkpoint interval in steps (>= 1); the
+                              reverse sweep recomputes w^n (Section 2.1: the adjoint
+                              needs the forward wavefield) segment by segment from
+                              the checkpoints.  0: history mode -- the forward sweep
+                              keeps every w^n, n = 0..nt-2, in the workspace and
+                              nothing is recomputed (one field update per shot and
+                              step fewer; the adjoint-bearing workspaces grow to
+                              (nt-1) ns fields, see fwi_workspace_size) */
   double inv_noise_var;    /* 1/sigma^2 weighting of the misfit */
 } fwi_geometry;
 
@@ -139,7 +146,8 @@ int fwi_workspace_size(const fwi_plan *p, int op, int batch, size_t *bytes);
  * option can change fwi_workspace_size: query it again afterwards. */
 enum {
   FWI_OPT_TWO_STEP_FORWARD = 0, /* 0/1: forward and recompute kernels advance two time
-                                   steps per launch (default 0; needs an even K) */
+                                   steps per launch (default 0; needs an even K or
+                                   history mode, as the two below) */
   FWI_OPT_TWO_STEP_BORN = 1,    /* 0/1: the same for forward + Born (default 1) */
   FWI_OPT_TWO_STEP_ADJOINT = 2, /* 0/1: the same for the adjoint (default 1) (*) */
   FWI_OPT_ADJ_VECTORS = 3,      /* right-hand sides per two-step adjoint workgroup,
@@ -167,7 +175,8 @@ int fwi_plan_set_option(fwi_plan *p, int option, int value);
 int fwi_plan_get_option(const fwi_plan *p, int option, int *value);
 
 /* Padded-grid geometry the kernels use (for tools and tests):
- * dims[0..5] = NZp, NXp, row pitch (floats), tile rows, tile columns, K. */
+ * dims[0..5] = NZp, NXp, row pitch (floats), tile rows, tile columns, K
+ * (nt - 1 in history mode). */
 int fwi_plan_dims(const fwi_plan *p, int32_t dims[6]);
 
 /* Forward map (Section 2): d[ns][nt][nr] = R u_s^n for every shot. */

@@ -61,6 +61,9 @@ int fwi::set_error(int code, const std::string &msg) { return fail(code, msg); }
 struct fwi_plan {
   Geo geo{};
   int K = 1, nseg = 1;
+  // ckpt_every == 0: the forward sweep keeps every w^n in the workspace (one
+  // segment of nt - 1 levels), so the reverse sweep recomputes nothing
+  bool hist = false;
   float dx = 0, dt = 0;
   double inv_noise_var = 1.0;
   std::vector<float> wavelet;
@@ -82,7 +85,9 @@ struct fwi_plan {
   // faster with fours than with pairs, B = 16 3 % slower)
   int adj_pair = 0;
   void apply_options() {
-    const bool even = K % 2 == 0;
+    // with the whole history kept no checkpoint level has to fall on a launch
+    // boundary, so two-step launches are allowed for any K
+    const bool even = hist || K % 2 == 0;
     ts_fwd = even && opt[FWI_OPT_TWO_STEP_FORWARD];
     ts_born = even && opt[FWI_OPT_TWO_STEP_BORN];
     ts_adj = even && opt[FWI_OPT_TWO_STEP_ADJOINT];
@@ -176,7 +181,7 @@ Layout layout(const fwi_plan *p, int op, int B) {
   if (needs_adj) {
     L.group = adjoint_group(p, Badj);
     L.G = (g.ns + L.group - 1) / L.group;
-    L.ckpt = take(F * 2 * g.ns * p->nseg);
+    L.ckpt = p->hist ? 0 : take(F * 2 * g.ns * p->nseg);
     L.wseg = take(F * g.ns * p->K);
     L.mu = alias_mu ? L.du : take(F * 2 * g.ns * Badj * msets);
     L.img = take((size_t)g.fs * sizeof(double) * L.G * Badj);
@@ -250,11 +255,15 @@ float *ckpt_slot(const fwi_plan *p, float *ckpt, int n) {
 }
 
 // Forward sweep n = 0..nt-2 on the fields at ws+L.u (and Born fields):
-// pairs of steps per launch while two remain, then single steps.
+// pairs of steps per launch while two remain, then single steps.  With
+// `store_ckpt` it leaves what the reverse sweep needs: the checkpoints, or in
+// history mode every w^n (n = 0..nt-2) in the segment buffer.
 int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, float *d_out,
                   float *dd_out, bool store_ckpt, hipStream_t st) {
   const Geo &g = p->geo;
-  float *ckpt = store_ckpt ? at<float>(ws, L.ckpt) : nullptr;
+  float *ckpt = store_ckpt && !p->hist ? at<float>(ws, L.ckpt) : nullptr;
+  float *whist = store_ckpt && p->hist ? at<float>(ws, L.wseg) : nullptr;
+  auto wlevel = [&](int n) { return whist ? whist + (size_t)n * g.ns * g.fs : nullptr; };
   float *u = at<float>(ws, L.u), *du = born ? at<float>(ws, L.du) : nullptr;
   const size_t us = set_stride(g, 1), dus = set_stride(g, B);
   int cur = 0, n = 0;
@@ -274,6 +283,8 @@ int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, floa
       a.duin = born ? du + cur * dus : nullptr;
       a.duout = born ? du + (cur ^ 1) * dus : nullptr;
       a.ck = ckpt_slot(p, ckpt, n + 2);
+      a.w_out0 = wlevel(n);
+      a.w_out1 = wlevel(n + 1);
       HIP_TRY(timed(p, born ? FWI_KERNEL_STEP_BORN : FWI_KERNEL_STEP, st,
                     [&] { return launch_step2(g, p->tabs, a, born, st); }));
     }
@@ -291,15 +302,17 @@ int forward_sweep(fwi_plan *p, const Layout &L, void *ws, int B, bool born, floa
     a.n = n;
     a.src_amp = src_amp(p, n);
     a.ck = ckpt_slot(p, ckpt, n + 1);
+    a.w_out = wlevel(n);
     HIP_TRY(timed(p, born ? FWI_KERNEL_STEP_BORN : FWI_KERNEL_STEP, st,
                   [&] { return launch_step(g, p->tabs, a, born, st); }));
   }
   return FWI_OK;
 }
 
-// Reverse sweep: segment-wise recompute of w^n from the checkpoints, then the
-// adjoint steps k = nt-1..0 with injection of r[B][ns][nt][nr].  Leaves the
-// partial images in ws+L.img.
+// Reverse sweep: segment-wise recompute of w^n from the checkpoints (skipped in
+// history mode: the forward sweep left every level), then the adjoint steps
+// k = nt-1..0 with injection of r[B][ns][nt][nr].  Leaves the partial images
+// in ws+L.img.
 int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
                   hipStream_t st) {
   const Geo &g = p->geo;
@@ -308,7 +321,7 @@ int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
   float *u = at<float>(ws, L.u), *mu = at<float>(ws, L.mu);
   HIP_TRY(launch_fill(mu, (long long)(ms * msets), st));
   HIP_TRY(launch_fill64(at<double>(ws, L.img), (long long)g.fs * L.G * B, st));
-  float *ckpt = at<float>(ws, L.ckpt);
+  float *ckpt = p->hist ? nullptr : at<float>(ws, L.ckpt);
   float *wseg = at<float>(ws, L.wseg);
   auto wbuf = [&](int n, int n0) { return wseg + (size_t)(n - n0) * g.ns * g.fs; };
   int mcur = 0;  // field set holding the adjoint state
@@ -317,8 +330,8 @@ int reverse_sweep(fwi_plan *p, const Layout &L, void *ws, int B, const float *r,
     const int n1 = std::min((j + 1) * p->K, g.nt - 1);
     // recompute on a copy so the checkpoints survive (the adjoint can be
     // repeated after one forward, see fwi_adjoint_resume)
-    HIP_TRY(launch_copy(u, ckpt + (size_t)j * 2 * g.ns * g.fs, (long long)us, st));
-    int ucur = 0, n = n0;
+    int ucur = 0, n = p->hist ? n1 : n0;
+    if (!p->hist) HIP_TRY(launch_copy(u, ckpt + (size_t)j * 2 * g.ns * g.fs, (long long)us, st));
     if (p->ts_fwd) {
       Step2Args f{};
       f.c = at<float>(ws, L.c);
@@ -397,7 +410,7 @@ int prologue(fwi_plan *p, const Layout &L, void *ws, const float *m, const float
                        born ? at<float>(ws, L.dc) : nullptr, ws_status(ws), st));
   HIP_TRY(launch_fill(at<float>(ws, L.u), (long long)set_stride(g, 1), st));
   if (born) HIP_TRY(launch_fill(at<float>(ws, L.du), (long long)set_stride(g, B), st));
-  if (adj) HIP_TRY(launch_fill(at<float>(ws, L.ckpt), (long long)g.fs * 2 * g.ns, st));
+  if (adj && !p->hist) HIP_TRY(launch_fill(at<float>(ws, L.ckpt), (long long)g.fs * 2 * g.ns, st));
   return FWI_OK;
 }
 
@@ -484,7 +497,7 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
     return fail(FWI_EINVAL, "dx and dt must be positive");
   if (!(G.kappa_max >= 0.f) || !(G.kappa_max < 0.5f))
     return fail(FWI_EINVAL, "kappa_max must be in [0, 0.5)");
-  if (G.ckpt_every < 1) return fail(FWI_EINVAL, "ckpt_every must be >= 1");
+  if (G.ckpt_every < 0) return fail(FWI_EINVAL, "ckpt_every must be >= 0");
   if (!G.src_zx || !G.rec_zx || !G.wavelet) return fail(FWI_EINVAL, "null geometry array");
   if (!(G.inv_noise_var >= 0.0) || !std::isfinite(G.inv_noise_var))
     return fail(FWI_EINVAL, "inv_noise_var must be finite and >= 0");
@@ -531,7 +544,8 @@ int fwi_plan_create(const fwi_geometry *gi, fwi_plan **out) {
   g.inv_dx = 1.0f / G.dx;
   p->dx = G.dx;
   p->dt = G.dt;
-  p->K = std::min(G.ckpt_every, G.nt - 1);
+  p->hist = G.ckpt_every == 0;
+  p->K = p->hist ? G.nt - 1 : std::min(G.ckpt_every, G.nt - 1);
   p->nseg = (G.nt - 1 + p->K - 1) / p->K;
   p->inv_noise_var = G.inv_noise_var;
   p->wavelet.assign(G.wavelet, G.wavelet + G.nt);

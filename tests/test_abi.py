@@ -78,7 +78,7 @@ def test_plan_host_logic(lib):
     ("nt", 1, b"nt"),
     ("dx", 0.0, b"dx"),
     ("kappa_max", 0.7, b"kappa_max"),
-    ("ckpt_every", 0, b"ckpt_every"),
+    ("ckpt_every", -1, b"ckpt_every"),
     ("src", [[0, 200]], b"source 0"),
     ("rec", [[-1, 3]], b"receiver 0"),
     ("nb", -1, b"nb"),
@@ -233,6 +233,44 @@ def test_plan_options(lib):
     assert lib.fwi_plan_set_option(h, fwi.OPTIONS["two_step_forward"], 1) == 0
     for kind in (fwi.KERNEL_STEP, fwi.KERNEL_STEP_BORN, fwi.KERNEL_ADJOINT):
         assert lib.fwi_kernel_steps(h, kind, ctypes.byref(steps)) == 0 and steps.value == 1
+    lib.fwi_plan_destroy(h)
+
+
+def test_history_mode_host_logic(lib):
+    """ckpt_every = 0 keeps the whole forward history: K reads nt - 1, the
+    adjoint-bearing workspaces hold (nt - 1) ns fields of w and no checkpoints,
+    the forward-only ones do not change, and the two-step kernels stay on
+    whatever the parity of nt - 1 (no checkpoint level has to fall on a launch
+    boundary)."""
+    geom, _, _ = synth.config_small()
+    sizes = {}
+    for ck in (50, 0):
+        geom.ckpt_every = ck
+        rc, h, _ = _plan(lib, geom)
+        assert rc == 0
+        dims = (ctypes.c_int32 * 6)()
+        assert lib.fwi_plan_dims(h, dims) == 0
+        nzp, nxp, pitch, tz, tx, K = list(dims)
+        assert K == (geom.nt - 1 if ck == 0 else 50)
+        fs = tz * 32 * pitch
+        for op in (fwi.FWI_OP_FORWARD, fwi.FWI_OP_GN_HVP):
+            n = ctypes.c_size_t()
+            assert lib.fwi_workspace_size(h, op, 2, ctypes.byref(n)) == 0
+            sizes[ck, op] = n.value
+        steps = ctypes.c_int32()
+        for kind in (fwi.KERNEL_STEP_BORN, fwi.KERNEL_ADJOINT):
+            assert lib.fwi_kernel_steps(h, kind, ctypes.byref(steps)) == 0 and steps.value == 2
+        lib.fwi_plan_destroy(h)
+    assert sizes[0, fwi.FWI_OP_FORWARD] == sizes[50, fwi.FWI_OP_FORWARD]
+    nseg = (geom.nt - 1 + 49) // 50
+    grow = 4 * fs * geom.ns * ((geom.nt - 1) - 50) - 4 * fs * 2 * geom.ns * nseg
+    assert abs(sizes[0, fwi.FWI_OP_GN_HVP] - sizes[50, fwi.FWI_OP_GN_HVP] - grow) <= 256
+    # an odd nt - 1 in history mode
+    geom.ckpt_every, geom.nt, geom.wavelet = 0, 300, geom.wavelet[:300]
+    rc, h, _ = _plan(lib, geom)
+    assert rc == 0
+    for kind in (fwi.KERNEL_STEP_BORN, fwi.KERNEL_ADJOINT):
+        assert lib.fwi_kernel_steps(h, kind, ctypes.byref(steps)) == 0 and steps.value == 2
     lib.fwi_plan_destroy(h)
 
 

@@ -240,6 +240,55 @@ def test_checkpoint_interval_invariance(torch):
     assert rel(outs[2], ref) < TOL_IMAGE and rel(outs[1], ref) < TOL_IMAGE
 
 
+def test_history_mode_equals_checkpoints(torch):
+    """ckpt_every = 0 keeps every forward level w^n (Section 2.1: the adjoint
+    needs the forward wavefield) instead of recomputing it from checkpoints.
+    The forward sweep and the recompute evaluate w^n with the same arithmetic,
+    so with nt - 1 odd (the adjoint pairs its steps alike in both modes) every
+    output equals the checkpointed plan's bit for bit; with nt - 1 even the
+    last checkpoint segment pairs the adjoint steps differently, which
+    regroups the FP32 image sums only.  Both match the oracle, and a repeated
+    adjoint on a kept forward (fwi_adjoint_resume) reads the history intact."""
+    from paper_2507_10804_amd import fwi
+
+    for nt in (230, 231):
+        g, m = tiny(nt=nt)
+        say(f"entry: history mode vs K=50, tiny nt={nt}")
+        V = synth.smooth_random_batch(g.nz, g.nx, seeds=[1, 2, 3], sigma=3.0)
+        dobs = oracle.forward(g, 1.02 * m)
+        r = synth.residual_noise((g.ns, g.nt, g.nr), seed=5)
+        out = {}
+        for K in (50, 0):
+            g.ckpt_every = K
+            p = make_plan(g)
+            mb, vb, db, rb = dev(torch, m), dev(torch, V), dev(torch, dobs), dev(torch, r)
+            hv = host(p.gn_hvp(mb, vb))
+            phi, gr = p.misfit_grad(mb, db)
+            phi2, gr2, hv2 = p.misfit_grad_hvp(mb, db, vb)
+            mig = host(p.adjoint(mb, rb))
+            ws = p.new_workspace(fwi.FWI_OP_ADJOINT, 1)
+            d = host(p.forward_keep(mb, ws))
+            res1, res2 = host(p.adjoint_resume(rb, ws)), host(p.adjoint_resume(rb, ws))
+            assert p.status() == 0
+            out[K] = dict(hv=hv, gr=host(gr), hv2=host(hv2), gr2=host(gr2), mig=mig, d=d,
+                          res1=res1, res2=res2, phi=float(phi), phi2=float(phi2))
+        h, c = out[0], out[50]
+        assert np.array_equal(h["d"], c["d"]) and h["phi"] == c["phi"] and h["phi2"] == c["phi2"]
+        assert np.array_equal(h["res1"], h["res2"]) and np.array_equal(h["res1"], h["mig"])
+        for k in ("hv", "gr", "hv2", "gr2", "mig"):
+            if nt % 2 == 0:
+                assert np.array_equal(h[k], c[k]), k
+            else:
+                assert rel(h[k], c[k]) < 1e-6, k
+        ref = oracle.gn_hvp(g, m, V)
+        eh = max(rel(h["hv"][b], ref[b]) for b in range(3))
+        _, gref = oracle.misfit_grad(g, m, dobs)
+        eg = rel(h["gr"], gref)
+        say(f"  history mode vs oracle: H v {eh:.2e}, gradient {eg:.2e}")
+        assert eh < TOL_IMAGE and eg < TOL_IMAGE
+        assert max(rel(h["hv2"][b], ref[b]) for b in range(3)) < TOL_IMAGE
+
+
 def test_two_step_matches_one_step_data(torch, small):
     """Forward and Born data are identical bit for bit whether the time loop
     advances one or two steps per launch (same arithmetic, same order)."""
