@@ -134,6 +134,9 @@ def gaussian_anomaly_model(nx=128, nz=128, dx=10.0, seed=0, background=2000.0,
     """Background velocity plus seeded Gaussian anomalies (C1 model)."""
     rng = np.random.default_rng(seed)
     Lx, Lz = nx * dx, nz * dx
+    if len(amps) > 1 and min_sep >= math.hypot(0.4 * Lz, 0.4 * Lx):
+        raise ValueError(f"anomaly centres in the middle 40 % of a {Lz:g} x {Lx:g} m model "
+                         f"cannot be {min_sep:g} m apart")
     while True:
         cz = rng.uniform(0.3, 0.7, size=len(amps)) * Lz
         cx = rng.uniform(0.3, 0.7, size=len(amps)) * Lx

@@ -364,6 +364,51 @@ def test_grid_smaller_than_tile(torch):
     _parity_all(torch, g, m)
 
 
+@pytest.mark.parametrize("shape", [(2, 3000), (3000, 2)])
+def test_extreme_aspect_grids(torch, shape):
+    """A model two cells thin and 3000 long, across and down: one tile row
+    (or column) with 54 tiles along the other axis, sources and receivers
+    in both thin rows."""
+    nz, nx = shape
+    say(f"case: {nz}x{nx} model, nb=4")
+    m = 2000.0 + 200.0 * np.sin(np.arange(nz * nx).reshape(nz, nx) / 37.0)
+    long_ax = max(nz, nx)
+    pos = np.array([[0, 100], [1, long_ax - 101], [1, long_ax // 2]])
+    src = pos[:2] if nz == 2 else pos[:2, ::-1]
+    rec = np.stack([np.arange(0, long_ax, 97) % 2, np.arange(0, long_ax, 97)], 1)
+    rec = rec if nz == 2 else rec[:, ::-1]
+    g = synth.make_geometry(nx, nz, nt=60, ns=2, rec_ix=[0], f0=60.0, v_nominal=2300.0, nb=4,
+                            src_zx=np.ascontiguousarray(src, dtype=np.int32))
+    g.rec_zx = np.ascontiguousarray(rec, dtype=np.int32)
+    _parity_all(torch, g, m)
+
+
+def test_maximum_batch(torch):
+    """The largest batch the ABI takes, B = 4096, on a small grid: by
+    linearity hv[b] = a_b H v_(b mod 8) for scaled copies of eight smooth
+    vectors, each checked against the oracle's product; B = 4097 is refused."""
+    from paper_2507_10804_amd import fwi
+
+    m = 2000.0 + 150.0 * synth.smooth_random((16, 20), seed=4, sigma=3.0) / 0.2
+    m = np.clip(m, 1700.0, 2300.0)
+    g = synth.make_geometry(20, 16, nt=60, ns=2, rec_ix=[1, 5, 9, 13, 17], f0=40.0,
+                            v_nominal=2300.0, nb=4)
+    say("case: fwi_gn_hvp B=4096, 20x16, 2 shots, nt=60")
+    bank = synth.smooth_random_batch(g.nz, g.nx, seeds=range(1, 9), sigma=2.0)
+    a = (1.0 + np.arange(4096)) / 4096.0
+    V = a[:, None, None] * bank[np.arange(4096) % 8]
+    p = make_plan(g)
+    hv = host(p.gn_hvp(dev(torch, m), dev(torch, V)))
+    assert p.status() == 0
+    ref = oracle.gn_hvp(g, m, bank)
+    errs = [rel(hv[b], a[b] * ref[b % 8]) for b in range(4096)]
+    say(f"  max rel-L2 over 4096 products {max(errs):.2e}")
+    assert max(errs) < TOL_IMAGE
+    with pytest.raises(fwi.FwiError) as ei:
+        p.gn_hvp(dev(torch, m), dev(torch, np.zeros((4097, g.nz, g.nx))))
+    assert ei.value.code == -1  # FWI_EINVAL
+
+
 def test_duplicate_receivers_and_tile_edges(torch):
     say("case: receivers duplicated and on tile boundaries")
     g, m = tiny(nx=150, nz=50, nt=150, nb=10)
