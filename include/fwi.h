@@ -154,8 +154,8 @@ enum {
                                    1..4; 0 (default): pairs (the last group ragged for
                                    odd counts), one group for 1 or 3 */
   FWI_OPT_ADJ_SHOT_GROUP = 4,   /* shots summed per adjoint workgroup; 0 (default):
-                                   the largest power of two <= 16 that keeps >= 4096
-                                   workgroups (*) */
+                                   the largest power of two <= 16 that keeps >= 1536
+                                   two-step (>= 4096 one-step) workgroups (*) */
   FWI_OPT_STEP_ORDER = 5,       /* workgroup order of the one-step forward kernels:  */
   FWI_OPT_BORN_ORDER = 6,       /*   0 shot-major (default), 1 tile-major, 2 blocked */
   FWI_OPT_ADJ_ORDER = 7,        /* the same for the one-step adjoint                  */

@@ -132,13 +132,21 @@ size_t set_stride(const Geo &g, int per_shot) { return (size_t)2 * g.ns * per_sh
 
 int adjoint_group(const fwi_plan *p, int B) {
   if (p->adj_group_override > 0) return std::min(p->adj_group_override, p->geo.ns);
-  // Enough workgroups to fill 256 CUs several times over, and as many shots
-  // per workgroup as that allows (fewer partial-image updates).
+  // As many shots per workgroup as keep enough workgroups in flight (fewer
+  // partial-image updates, and each shot reuses the workgroup's coefficient
+  // and image tiles), at most 16.  Two-step kernel (512 threads, two per CU):
+  // at least 1536 workgroups, three rounds of the 512 slots.  Measured on
+  // 921 x 301 with 64 shots (198 tiles), per two-step launch: one vector group
+  // (B = 1 or 2) takes 177 / 158 / 157 / 181 us with groups of 2 / 4 / 8 / 16
+  // (16 leaves 792 workgroups); nine groups (B + 1 = 17) 2120 / 1977 / 1949 us
+  // with 4 / 8 / 16; 32 groups (B = 64) 7821 / 7322 / 7110 us.  One-step
+  // kernel (256 threads): at least 4096 workgroups.
   const int nbg = p->ts_adj ? (B + p->adj_nb(B) - 1) / p->adj_nb(B) : B;
-  const long long base = (long long)p->geo.ntiles * nbg;
+  const long long base = (long long)(p->ts_adj ? p->geo.ntiles2 : p->geo.ntiles) * nbg;
+  const long long need = p->ts_adj ? 1536 : 4096;
   int group = 1;
   while (group < 16 && group * 2 <= p->geo.ns &&
-         base * ((p->geo.ns + group * 2 - 1) / (group * 2)) >= 4096)
+         base * ((p->geo.ns + group * 2 - 1) / (group * 2)) >= need)
     group *= 2;
   return group;
 }
