@@ -136,6 +136,30 @@ def test_probe_session_graph_replays(torch):
     assert rel(host(sess.run(dev(torch, combs))), oracle.gn_hvp(g, m, combs)) < 1e-4
 
 
+def test_probe_session_history_mode(torch):
+    """A probe session on a plan that keeps the whole forward history
+    (ckpt_every = 0): the captured call stores every w^n in the forward sweep
+    and recomputes nothing, and its replays equal the eager call and the
+    checkpointed plan's products bit for bit (nt - 1 odd: the adjoint pairs
+    its steps alike in both modes)."""
+    from paper_2507_10804_amd import fwi, probing
+    say("entry: ProbeSession graph capture tiny, history mode, B=4")
+    g, m = tiny(nt=160)
+    rad = synth.rademacher_smoothed(g.nz, g.nx, seeds=[300, 301, 302, 303], sigma=2.0)
+    ckpt = host(fwi.Plan(g).gn_hvp(dev(torch, m), dev(torch, rad)))
+    g.ckpt_every = 0
+    plan = fwi.Plan(g)
+    assert plan.K == g.nt - 1
+    sess = probing.ProbeSession(plan, dev(torch, m), batch=4, use_graph=True)
+    for rep in range(3):
+        out = host(sess.run(dev(torch, rad)))
+        torch.cuda.synchronize()
+        assert np.array_equal(out, ckpt), f"replay {rep} differs from the checkpointed plan"
+        _ = (dev(torch, rad) * 2).sum().item()
+    assert np.array_equal(host(plan.gn_hvp(dev(torch, m), dev(torch, rad))), ckpt)
+    assert plan.status() == 0
+
+
 def test_probe_session_survives_workspace_release(torch):
     """A session keeps its own workspace: after the plan drops its cached
     workspaces and the memory is handed to another tensor, replays still
