@@ -78,11 +78,7 @@ struct fwi_plan {
   // option where K is even (the checkpoint levels must fall on launch
   // boundaries), else single steps
   bool ts_fwd = false, ts_born = true, ts_adj = true;
-  // vectors per two-step adjoint workgroup (1..4; 0 = by batch): pairs for
-  // even batches; for odd batches of 5 or more (the fused gradient + B
-  // products has B + 1 right-hand sides) fours, which leave one short group
-  // instead of a lone vector in a pair's slot (measured: B + 1 = 17 runs 7 %
-  // faster with fours than with pairs, B = 16 3 % slower)
+  // vectors per two-step adjoint workgroup (1..4; 0 = by batch, see adj_nb)
   int adj_pair = 0;
   void apply_options() {
     // with the whole history kept no checkpoint level has to fall on a launch
