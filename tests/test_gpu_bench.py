@@ -13,7 +13,8 @@ pytestmark = pytest.mark.gpu
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-@pytest.mark.parametrize("extra", [[], ["--separate"]], ids=["fused", "separate"])
+@pytest.mark.parametrize("extra", [[], ["--separate"], ["--ckpt-every", "0"]],
+                         ids=["fused", "separate", "history"])
 def test_bench_line_fields(extra):
     print(f"case: bench.py {' '.join(extra)} on 921x301, 4 shots, nt=100, B=2, one step",
           flush=True)
@@ -31,6 +32,7 @@ def test_bench_line_fields(extra):
     assert d["n_gpus"] == 1 and d["steps"] == 1 and d["warmup"] == 0
     assert d["unit"] == "Hv/s" and d["higher_is_better"] is True and d["vs_baseline"] is None
     assert d["value"] > 0 and d["ms_per_step"] > 0 and "workload" in d["config"]
+    assert d["config"]["ckpt_every"] == (0 if "--ckpt-every" in extra else 50)
     ro = d["roofline"]
     for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert key in ro, key
