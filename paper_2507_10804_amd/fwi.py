@@ -182,7 +182,10 @@ class Plan:
     own (``ws=``).  Calls from several threads on different streams are safe
     when each brings its own workspace and telemetry is off.  ``options``
     maps names of :data:`OPTIONS` to values (the plan's tuning options, set
-    before the device block is bound).
+    before the device block is bound).  ``geom.ckpt_every = 0`` keeps the
+    whole forward history in the adjoint-bearing workspaces instead of
+    checkpoints (no recompute; ``self.K`` then reads nt - 1 and
+    ``self.history`` is True).
     """
 
     def __init__(self, geom, device=None, options=None):
@@ -208,6 +211,7 @@ class Plan:
         dims = (ctypes.c_int32 * 6)()
         _check(self.lib.fwi_plan_dims(h, dims))
         self.nzp, self.nxp, self.pitch, self.tiles_z, self.tiles_x, self.K = list(dims)
+        self.history = int(geom.ckpt_every) == 0
 
     # -- plumbing ---------------------------------------------------------
     def __del__(self):

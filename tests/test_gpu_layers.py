@@ -149,7 +149,7 @@ def test_probe_session_history_mode(torch):
     ckpt = host(fwi.Plan(g).gn_hvp(dev(torch, m), dev(torch, rad)))
     g.ckpt_every = 0
     plan = fwi.Plan(g)
-    assert plan.K == g.nt - 1
+    assert plan.K == g.nt - 1 and plan.history
     sess = probing.ProbeSession(plan, dev(torch, m), batch=4, use_graph=True)
     for rep in range(3):
         out = host(sess.run(dev(torch, rad)))
