@@ -409,6 +409,31 @@ def test_maximum_batch(torch):
     assert ei.value.code == -1  # FWI_EINVAL
 
 
+def test_grid_one_column_past_whole_tiles(torch):
+    """NXp = 2 * 64 + 1 with a sponge: the one-step kernels' last tile column
+    holds the grid's last column alone (as the 961 padded columns of the
+    921-column workloads do).  Forward data equal the two-step kernel's bit
+    for bit, and data, Born data and the product match the oracle, with
+    sources and receivers at the model's right edge; the product does not
+    depend on the checkpoint interval (odd K runs every kernel one step at a
+    time)."""
+    say("case: 40x89 model, nb=20 (NXp = 129)")
+    g, m = tiny(nx=89, nz=40, nt=150, nb=20)
+    g.src_zx = np.array([[1, 88], [20, 44], [39, 0]], dtype=np.int32)
+    g.rec_zx = np.array([[1, 88], [39, 88], [20, 87], [1, 0], [10, 64]], dtype=np.int32)
+    mb = dev(torch, m)
+    d1 = host(_plan_with(g, "011").forward(mb))
+    d2 = host(_plan_with(g, "111").forward(mb))
+    assert np.array_equal(d1, d2)
+    _parity_all(torch, g, m)
+    v = synth.smooth_random(m.shape, seed=1, sigma=2.0)
+    hv = {}
+    for K in (50, 7):
+        g.ckpt_every = K
+        hv[K] = host(make_plan(g).gn_hvp(mb, dev(torch, v)))
+    assert rel(hv[7], hv[50]) < 1e-6
+
+
 def test_duplicate_receivers_and_tile_edges(torch):
     say("case: receivers duplicated and on tile boundaries")
     g, m = tiny(nx=150, nz=50, nt=150, nb=10)
