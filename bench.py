@@ -996,6 +996,12 @@ def main():
     fused = not args.separate
     if fused:
         ws_gb = plan.workspace_bytes(fwi.FWI_OP_GRAD_HVP, B) / 1e9
+    free_gb = torch.cuda.mem_get_info(dev)[0] / 1e9
+    if ws_gb > free_gb:
+        print(f"bench.py: the step needs {ws_gb:.1f} GB of workspace and {free_gb:.1f} GB are free"
+              + (" (history mode keeps every forward level: use fewer shots or steps, or a "
+                 "checkpoint interval)" if hist else ""), file=sys.stderr)
+        sys.exit(2)
 
     def step():
         if fused:

@@ -44,3 +44,16 @@ def test_bench_line_fields(extra):
     for key in ("value", "unit", "cores", "kind", "sample"):
         assert key in cb, key
     assert cb["kind"] == "oracle" and cb["value"] > 0 and 1 <= cb["cores"] <= 4
+
+
+def test_bench_refuses_a_workspace_larger_than_free_memory():
+    """History mode on the full 64-shot, 4000-step workload would keep
+    357 GB of forward levels: the bench says so and exits with status 2
+    before allocating the workspace."""
+    print("case: bench.py --ckpt-every 0 on the full 921x301, 64-shot, 4000-step workload",
+          flush=True)
+    cmd = [sys.executable, "-u", os.path.join(ROOT, "bench.py"), "--ckpt-every", "0",
+           "--steps", "1", "--warmup", "0", "--no-cpu-baseline"]
+    r = subprocess.run(cmd, cwd=ROOT, capture_output=True, text=True, timeout=600)
+    assert r.returncode == 2, r.stderr[-3000:]
+    assert "GB of workspace" in r.stderr and "history mode" in r.stderr
