@@ -434,6 +434,40 @@ def test_grid_one_column_past_whole_tiles(torch):
     assert rel(hv[7], hv[50]) < 1e-6
 
 
+@pytest.mark.parametrize("seed", range(8))
+def test_seeded_random_geometries(torch, seed):
+    """Eight seeded small problems with every size drawn: grid 5..150 by
+    5..150 cells, sponge 0..12 cells, 1..4 shots anywhere in the model with a
+    receiver on every shot cell (so every data set holds the direct arrival)
+    and 1..9 more anywhere, 30..120 steps, checkpoint interval 1..60 or the
+    whole history (0), 1..5 vectors.  Forward and Born data and the products
+    against the oracle."""
+    rng = np.random.default_rng(1000 + seed)
+    nz, nx = (int(x) for x in rng.integers(5, 151, size=2))
+    nb = int(rng.integers(0, 13))
+    ns, nr = int(rng.integers(1, 5)), int(rng.integers(1, 10))
+    nt = int(rng.integers(30, 121))
+    K = int(rng.choice([0, 1, 2, 5, 7, 16, 60]))
+    B = int(rng.integers(1, 6))
+    say(f"case: seed {seed}: {nz}x{nx}, nb={nb}, ns={ns}, nr={nr}, nt={nt}, K={K}, B={B}")
+    m = 2000.0 + 200.0 * synth.smooth_random((nz, nx), seed=seed, sigma=2.0) / 0.2
+    m = np.clip(m, 1700.0, 2300.0)
+    cells = lambda n: np.stack([rng.integers(0, nz, n), rng.integers(0, nx, n)], 1).astype(np.int32)
+    src = cells(ns)
+    g = synth.make_geometry(nx, nz, nt=nt, ns=ns, rec_ix=[0], f0=60.0, v_nominal=2300.0, nb=nb,
+                            src_zx=src, ckpt_every=K)
+    g.rec_zx = np.ascontiguousarray(np.concatenate([src, cells(nr)]), dtype=np.int32)
+    V = synth.smooth_random_batch(nz, nx, seeds=range(50, 50 + B), sigma=1.5)
+    p = make_plan(g)
+    mb = dev(torch, m)
+    assert rel(host(p.forward(mb)), oracle.forward(g, m)) < TOL_DATA
+    dd = host(p.born(mb, dev(torch, V)))
+    assert max(rel(dd[b], oracle.born(g, m, V[b])) for b in range(B)) < TOL_DATA
+    hv, ref = host(p.gn_hvp(mb, dev(torch, V))), oracle.gn_hvp(g, m, V)
+    assert max(rel(hv[b], ref[b]) for b in range(B)) < TOL_IMAGE
+    assert p.status() == 0
+
+
 def test_duplicate_receivers_and_tile_edges(torch):
     say("case: receivers duplicated and on tile boundaries")
     g, m = tiny(nx=150, nz=50, nt=150, nb=10)
