@@ -440,8 +440,9 @@ def test_seeded_random_geometries(torch, seed):
     5..150 cells, sponge 0..12 cells, 1..4 shots anywhere in the model with a
     receiver on every shot cell (so every data set holds the direct arrival)
     and 1..9 more anywhere, 30..120 steps, checkpoint interval 1..60 or the
-    whole history (0), 1..5 vectors.  Forward and Born data and the products
-    against the oracle."""
+    whole history (0), 1..5 vectors.  Forward and Born data, the migration of
+    a random residual and the products against the oracle; the fused misfit +
+    gradient + products pass against the separate calls."""
     rng = np.random.default_rng(1000 + seed)
     nz, nx = (int(x) for x in rng.integers(5, 151, size=2))
     nb = int(rng.integers(0, 13))
@@ -463,8 +464,15 @@ def test_seeded_random_geometries(torch, seed):
     assert rel(host(p.forward(mb)), oracle.forward(g, m)) < TOL_DATA
     dd = host(p.born(mb, dev(torch, V)))
     assert max(rel(dd[b], oracle.born(g, m, V[b])) for b in range(B)) < TOL_DATA
+    r = synth.residual_noise((g.ns, g.nt, g.nr), seed=seed)
+    assert rel(host(p.adjoint(mb, dev(torch, r))), oracle.adjoint(g, m, r)) < TOL_IMAGE
     hv, ref = host(p.gn_hvp(mb, dev(torch, V))), oracle.gn_hvp(g, m, V)
     assert max(rel(hv[b], ref[b]) for b in range(B)) < TOL_IMAGE
+    dobs = dev(torch, oracle.forward(g, 1.03 * m))
+    phi, gr, hv2 = p.misfit_grad_hvp(mb, dobs, dev(torch, V))
+    phi_s, gr_s = p.misfit_grad(mb, dobs)
+    assert float(phi) == float(phi_s)
+    assert rel(host(gr), host(gr_s)) < 1e-6 and rel(host(hv2), hv) < 1e-6
     assert p.status() == 0
 
 
