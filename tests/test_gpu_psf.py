@@ -6,7 +6,7 @@
   gives ~1e-6);
 * shapes cover several 32 x 32 sub-tiles per cell, boundary strips wider
   than a sub-tile, ragged edges, one-centre lattices, half-widths 0 and 32,
-  one-cell grids and batches;
+  one-cell grids and batches, and six seeded random lattices;
 * end to end on a small wave problem: comb Hessian products on the GPU,
   extraction and apply against the oracle's products, extraction and apply
   (the Hessian-product tolerance 1e-4 bounds it);
@@ -79,6 +79,51 @@ def test_extract_bit_exact(case):
     got = gpsf.extract(g, dev(torch, hv)).cpu().numpy()
     ref = P.extract(g, hv.astype(np.float64)).astype(np.float32)
     assert np.array_equal(got, ref)
+
+
+def _random_grid(seed):
+    """A seeded PSF lattice with every parameter drawn, redrawn until the
+    library's own rules accept it."""
+    from paper_2507_10804_amd import fwi
+    from paper_2507_10804_amd import psf as gpsf
+
+    rng = np.random.default_rng(500 + seed)
+    while True:
+        nz, nx = (int(x) for x in rng.integers(1, 181, size=2))
+        sz, sx = (int(x) for x in rng.integers(1, 61, size=2))
+        oz, ox = int(rng.integers(0, min(sz, nz))), int(rng.integers(0, min(sx, nx)))
+        nzc = (nz - 1 - oz) // sz + 1  # the whole lattice that fits
+        nxc = (nx - 1 - ox) // sx + 1
+        g = synth.PsfGrid(nz, nx, oz, ox, sz, sx, nzc, nxc, int(rng.integers(0, 33)),
+                          int(rng.integers(1, 4)))
+        try:
+            gpsf.check(g)
+            return g
+        except fwi.FwiError:
+            continue
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_seeded_random_lattices(seed):
+    """Six seeded lattices with every size drawn (grid 1..180 cells a side,
+    spacing 1..60, offsets below the spacing, the whole lattice that fits,
+    half-width 0..32, comb stride 1..3): the apply against the oracle for two
+    vectors, extraction bit for bit."""
+    import torch
+    from paper_2507_10804_amd import psf as gpsf
+
+    g = _random_grid(seed)
+    say(f"case: seed {seed}: {g}")
+    rng = np.random.default_rng(seed)
+    psf = rng.standard_normal((g.r, g.width, g.width)).astype(np.float32)
+    v = rng.standard_normal((2, g.nz, g.nx)).astype(np.float32)
+    out = gpsf.apply(g, dev(torch, psf), dev(torch, v)).double().cpu().numpy()
+    for b in range(2):
+        ref = P.apply_rows(g, psf.astype(np.float64), v[b].astype(np.float64))
+        assert rel(out[b], ref) < 1e-5
+    hv = rng.standard_normal((g.ncombs, g.nz, g.nx)).astype(np.float32)
+    got = gpsf.extract(g, dev(torch, hv)).cpu().numpy()
+    assert np.array_equal(got, P.extract(g, hv.astype(np.float64)).astype(np.float32))
 
 
 def test_argument_errors():
