@@ -86,6 +86,34 @@ def test_apply_matches_oracle(shape):
         assert e < 1e-5
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_seeded_random_grids(seed):
+    """Six seeded FFT grids with every size drawn: model 1..160 rows by
+    1..2000 columns, 0..40 cells of padding (the FFT lengths are the next
+    2-3-5 numbers, up to 2048), 1..8 terms, 1..5 vectors: the apply against
+    the oracle."""
+    import torch
+    from paper_2507_10804_amd import symbol as S
+
+    rng = np.random.default_rng(700 + seed)
+    while True:
+        nz, nx = int(rng.integers(1, 161)), int(rng.integers(1, 2001))
+        G = synth.symbol_grid(nz, nx, float(rng.uniform(1.0, 20.0)), int(rng.integers(0, 41)),
+                              r=8, rho0=float(rng.uniform(0.0, 0.1)))
+        if G.mx <= 2048 and G.mz <= 2048:
+            break
+    S.check(G)
+    T, B = int(rng.integers(1, 9)), int(rng.integers(1, 6))
+    A = r32(rng.standard_normal((T, nz, nx)) + 1j * rng.standard_normal((T, nz, nx)))
+    M = r32(rng.standard_normal((T, G.mz, G.mx)) + 1j * rng.standard_normal((T, G.mz, G.mx)))
+    v = r32(rng.standard_normal((B, nz, nx)))
+    say(f"case: seed {seed}: fwi_symbol_apply {nz}x{nx} on {G.mz}x{G.mx}, T={T}, B={B}")
+    got = host(S.Symbol(G).apply(dev(torch, A, torch.complex64), dev(torch, M, torch.complex64),
+                                 0.75, dev(torch, v)))
+    for b in range(B):
+        assert crel(got[b], 0.75 * D.symbol_apply(G, A, M, v[b])) < 1e-5
+
+
 @pytest.mark.parametrize("split", [1, 2, 4])
 def test_apply_blend_splits(split):
     """The blend with 1, 2 or 4 wavefronts sharing one vector's terms (the
