@@ -40,8 +40,19 @@ def host(x):
     return x.detach().double().cpu().numpy()
 
 
+def _random_prior_shapes(count):
+    """Seeded prior grids with every parameter drawn: 1..200 by 1..400 cells,
+    spacing 1..20 m, correlation length 2..50 cells, deviation 0.5..300."""
+    rng = np.random.default_rng(900)
+    out = []
+    for _ in range(count):
+        nz, nx, h = int(rng.integers(1, 201)), int(rng.integers(1, 401)), float(rng.uniform(1, 20))
+        out.append((nz, nx, h, h * float(rng.uniform(2, 50)), float(rng.uniform(0.5, 300))))
+    return out
+
+
 @pytest.mark.parametrize("shape", [(37, 45, 10.0, 80.0, 5.0), (301, 921, 10.0, 500.0, 200.0),
-                                   (1, 7, 3.0, 10.0, 1.0)])
+                                   (1, 7, 3.0, 10.0, 1.0)] + _random_prior_shapes(4))
 def test_prior_operators(shape):
     import torch
     from paper_2507_10804_amd import lowrank as glr
